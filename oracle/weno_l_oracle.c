@@ -1,0 +1,451 @@
+/*
+ * Reference oracle for the arc-length WENO scheme (WENO-L) for Hamilton-Jacobi
+ * equations (Rathan & Biswas, arXiv:1909.13263).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, scalar FP64 code written to be read
+ * against the paper.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the GPU library never links or calls it and
+ * the two share no source.
+ *
+ * What is followed where (the paper's Section 2 unless noted):
+ *   orc_candidates        Step 2, the three third-order formulas for phi_x^{-,k}
+ *   indicator_poly        Step 4, the coefficients b_i^k, c_i^k of p_i^k
+ *   arc_length            Step 4, eq. (length) and the primitive I[b,c,z]
+ *   weno_l_minus          Steps 2-4, eqs. (WLOC1) and (newbeta), linear weights of Step 3
+ *   weno_l_plus           Step 2, "symmetric procedure with respect to x_i"
+ *   hamiltonian           the test problems of Section 3 (Examples 3.1-3.4, 3.6, 3.12)
+ *   dissipation           eq. (LF): alpha = max |H_1| (global box reading, see below)
+ *   lax_friedrichs        eq. (LF)
+ *   rk3_step              Step 5 (TVD Runge-Kutta, third order)
+ *
+ * Readings where the paper is silent or garbled (each is also listed in the
+ * design notes of the repository):
+ *   - b_i^k, c_i^k are written with x_i as a parameter and evaluated with the
+ *     local origin x_i = 0: the arc length depends only on p', which is
+ *     translation invariant, and the global coordinate cancels badly.
+ *   - p_i^k is the quadratic p_{k,1}^- of Step 2; its derivative b + 2 c x is the
+ *     second derivative of the cubic interpolating phi on the sub-stencil.
+ *   - The primitive difference I(x_i) - I(x_{i-1}) is evaluated as
+ *     dx * mean_{s in [s_lo, s_hi]} sqrt(1+s^2), with the mean rearranged so that
+ *     it does not cancel; c = 0 is the limit s_lo = s_hi of the same expression.
+ *   - alpha is the maximum of |H_1| (|H_2| for y) over the box spanned by the
+ *     current step's derivative ranges [A,B] x [C,D], held for all three stages.
+ *     PARITY UNPINNED by the paper as a reading; its closed forms are pinned by
+ *     brute-force sampling of the box in the tests.
+ *   - dt = cfl / (alpha_x/dx + alpha_y/dy), clamped to t_final - t (the paper
+ *     gives only the CFL number).  PARITY UNPINNED by the paper (a reading).
+ *   - Boundaries: periodic wrap, or linear extrapolation into three ghosts.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EPS 1.0e-6 /* epsilon of eq. (WLOC1) */
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1 };
+enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3 };
+
+typedef struct {
+    int32_t dim;       /* 1 or 2 */
+    int32_t bc_x;      /* ORC_BC_* */
+    int32_t bc_y;
+    int32_t ham;       /* ORC_H_* */
+    int64_t nx;        /* points along x (fastest index) */
+    int64_t ny;        /* points along y (1 in 1-D) */
+    double dx;
+    double dy;
+    double hp[4];      /* Hamiltonian parameters, see hamiltonian() */
+} orc_problem;
+
+typedef struct {
+    int64_t steps;
+    double t;
+    double last_dt;
+    double alpha_x;
+    double alpha_y;
+    double range[4];   /* A, B, C, D of the last step */
+} orc_info;
+
+/* ---------------------------------------------------------------------------
+ * Step 2: third-order candidates phi_{x,i}^{-,k} from the forward differences
+ * v[0..4] = Delta^+ phi_{i-3}, ..., Delta^+ phi_{i+1}.
+ * ------------------------------------------------------------------------- */
+void orc_candidates(const double v[5], double q[3])
+{
+    q[0] = (1.0 / 3.0) * v[0] - (7.0 / 6.0) * v[1] + (11.0 / 6.0) * v[2];
+    q[1] = -(1.0 / 6.0) * v[1] + (5.0 / 6.0) * v[2] + (1.0 / 3.0) * v[3];
+    q[2] = (1.0 / 3.0) * v[2] + (5.0 / 6.0) * v[3] - (1.0 / 6.0) * v[4];
+}
+
+/* ---------------------------------------------------------------------------
+ * Step 4: coefficients of p_i^k(x) = a + b x + c x^2 as printed, in terms of
+ * f[0..5] = phi_{i-3}, ..., phi_{i+2} and the abscissa x_i.
+ * ------------------------------------------------------------------------- */
+static void indicator_poly(const double f[6], double dx, double xi, double b[3], double c[3])
+{
+    const double pm3 = f[0], pm2 = f[1], pm1 = f[2], p0 = f[3], pp1 = f[4], pp2 = f[5];
+    const double d3 = 6.0 * dx * dx * dx;
+    b[0] = (-6.0 * dx * pm3 + 24.0 * dx * pm2 - 30.0 * dx * pm1 + 12.0 * dx * p0
+            + 6.0 * xi * pm3 - 18.0 * xi * pm2 + 18.0 * xi * pm1 - 6.0 * xi * p0) / d3;
+    c[0] = (-3.0 * pm3 + 9.0 * pm2 - 9.0 * pm1 + 3.0 * p0) / d3;
+    b[1] = (6.0 * dx * pm1 - 12.0 * dx * p0 + 6.0 * dx * pp1
+            + 6.0 * xi * pm2 - 18.0 * xi * pm1 + 18.0 * xi * p0 - 6.0 * xi * pp1) / d3;
+    c[1] = (-3.0 * pm2 + 9.0 * pm1 - 9.0 * p0 + 3.0 * pp1) / d3;
+    b[2] = (6.0 * dx * pm1 - 12.0 * dx * p0 + 6.0 * dx * pp1
+            + 6.0 * xi * pm1 - 18.0 * xi * p0 + 18.0 * xi * pp1 - 6.0 * xi * pp2) / d3;
+    c[2] = (-3.0 * pm1 + 9.0 * p0 - 9.0 * pp1 + 3.0 * pp2) / d3;
+}
+
+/* Antiderivative of sqrt(1+s^2): F(s) = (s sqrt(1+s^2) + asinh s) / 2. */
+static double prim_sqrt1p(double s)
+{
+    return 0.5 * (s * sqrt(1.0 + s * s) + asinh(s));
+}
+
+/* Mean of sqrt(1+s^2) over s between a and b.  Equal to (F(b)-F(a))/(b-a);
+ * when a and b have the same sign both halves of that quotient are rewritten
+ * with the identities
+ *   b sqrt(1+b^2) - a sqrt(1+a^2) = (b-a)(a+b)(1+a^2+b^2) / (a sqrt(1+a^2) + b sqrt(1+b^2))
+ *   asinh b - asinh a             = asinh(w),  w = (b-a)(a+b) / (a sqrt(1+b^2) + b sqrt(1+a^2))
+ * so that no difference of nearly equal numbers is formed. */
+static double mean_sqrt1p(double a, double b)
+{
+    const double A = sqrt(1.0 + a * a);
+    const double B = sqrt(1.0 + b * b);
+    if (a == b)
+        return A;
+    if (a * b > 0.0) {
+        const double t1 = (a + b) * (1.0 + a * a + b * b) / (a * A + b * B);
+        const double r = (a + b) / (a * B + b * A);
+        const double w = (b - a) * r;
+        const double t2 = (w == 0.0) ? r : r * asinh(w) / w;
+        return 0.5 * (t1 + t2);
+    }
+    /* opposite signs (or a zero end): F is odd and increasing, nothing cancels */
+    return (prim_sqrt1p(b) - prim_sqrt1p(a)) / (b - a);
+}
+
+/* eq. (length): arc length of a polynomial P with P'(x) = b + 2 c x over
+ * [x_lo, x_hi], i.e. I[b,c,x_hi] - I[b,c,x_lo]. */
+double orc_arc_length(double b, double c, double x_lo, double x_hi)
+{
+    const double s_lo = b + 2.0 * c * x_lo;
+    const double s_hi = b + 2.0 * c * x_hi;
+    return (x_hi - x_lo) * mean_sqrt1p(s_lo, s_hi);
+}
+
+/* ---------------------------------------------------------------------------
+ * Steps 2-4: left-biased fifth-order WENO-L derivative phi_{x,i}^- from the six
+ * point values f[0..5] = phi_{i-3}, ..., phi_{i+2}.  Optionally returns the
+ * smoothness indicators beta_k and the nonlinear weights omega_k.
+ * ------------------------------------------------------------------------- */
+double orc_weno_l_minus(const double f[6], double dx, double *beta_out, double *omega_out)
+{
+    static const double d[3] = {1.0 / 10.0, 6.0 / 10.0, 3.0 / 10.0}; /* Step 3 */
+    double v[5], q[3], b[3], c[3], beta[3], alpha[3], omega[3];
+    int k;
+
+    for (k = 0; k < 5; ++k)
+        v[k] = (f[k + 1] - f[k]) / dx; /* Delta^+ phi_{i-3+k} */
+    orc_candidates(v, q);
+
+    /* eq. (newbeta): beta_k = (length of p_i^k over [x_{i-1}, x_i])^2, local origin x_i = 0 */
+    indicator_poly(f, dx, 0.0, b, c);
+    for (k = 0; k < 3; ++k) {
+        const double L = orc_arc_length(b[k], c[k], -dx, 0.0);
+        beta[k] = L * L;
+    }
+
+    /* eq. (WLOC1) */
+    double sum = 0.0;
+    for (k = 0; k < 3; ++k) {
+        alpha[k] = d[k] / ((ORC_EPS + beta[k]) * (ORC_EPS + beta[k]));
+        sum += alpha[k];
+    }
+    double u = 0.0;
+    for (k = 0; k < 3; ++k) {
+        omega[k] = alpha[k] / sum;
+        u += omega[k] * q[k];
+    }
+    if (beta_out)
+        for (k = 0; k < 3; ++k) beta_out[k] = beta[k];
+    if (omega_out)
+        for (k = 0; k < 3; ++k) omega_out[k] = omega[k];
+    return u;
+}
+
+/* Right-biased phi_{x,i}^+ by the symmetric procedure about x_i: reflect the
+ * data (x -> 2 x_i - x), take the left-biased derivative, and change its sign
+ * (a derivative changes sign under the reflection).  g[0..5] = phi_{i-2}, ..., phi_{i+3}. */
+double orc_weno_l_plus(const double g[6], double dx, double *beta_out, double *omega_out)
+{
+    double r[6];
+    for (int k = 0; k < 6; ++k)
+        r[k] = g[5 - k]; /* phi_{i+3}, ..., phi_{i-2} */
+    return -orc_weno_l_minus(r, dx, beta_out, omega_out);
+}
+
+/* ---------------------------------------------------------------------------
+ * Ghost values: three per side.  periodic wraps; extrapolation continues the
+ * line through the two end points.
+ * ------------------------------------------------------------------------- */
+static void fill_line(const double *src, int64_t stride, int64_t n, int bc, double *ext /* n+6 */)
+{
+    for (int64_t i = 0; i < n; ++i)
+        ext[i + 3] = src[i * stride];
+    for (int g = 1; g <= 3; ++g) {
+        if (bc == ORC_BC_PERIODIC) {
+            ext[3 - g] = src[((n - g) % n) * stride];
+            ext[n + 2 + g] = src[((g - 1) % n) * stride];
+        } else {
+            const double f0 = src[0], f1 = src[stride];
+            const double fl = src[(n - 1) * stride], fl1 = src[(n - 2) * stride];
+            ext[3 - g] = f0 - (double)g * (f1 - f0);
+            ext[n + 2 + g] = fl + (double)g * (fl - fl1);
+        }
+    }
+}
+
+static void line_derivatives(const double *ext, int64_t n, double h, double *dm, int64_t sm,
+                             double *dp, int64_t sp)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        /* ext[i+3] is node i: window phi_{i-3..i+2} starts at ext[i], phi_{i-2..i+3} at ext[i+1] */
+        dm[i * sm] = orc_weno_l_minus(ext + i, h, NULL, NULL);
+        dp[i * sp] = orc_weno_l_plus(ext + i + 1, h, NULL, NULL);
+    }
+}
+
+/* u-, u+ (along x) for every node, and v-, v+ (along y) in 2-D.  Arrays are
+ * row-major, x fastest.  Returns 0, or -1 on bad arguments. */
+int orc_derivatives(const orc_problem *p, const double *phi, double *um, double *up, double *vm,
+                    double *vp)
+{
+    if (!p || !phi || !um || !up || p->nx < 4 || p->ny < 1)
+        return -1;
+    if (p->dim == 2 && (!vm || !vp || p->ny < 4))
+        return -1;
+    const int64_t nx = p->nx, ny = p->ny;
+    int64_t j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < ny; ++j) {
+        double *ext = (double *)malloc((size_t)(nx + 6) * sizeof(double));
+        fill_line(phi + j * nx, 1, nx, p->bc_x, ext);
+        line_derivatives(ext, nx, p->dx, um + j * nx, 1, up + j * nx, 1);
+        free(ext);
+    }
+    if (p->dim == 2) {
+        int64_t i;
+#pragma omp parallel for schedule(static)
+        for (i = 0; i < nx; ++i) {
+            double *ext = (double *)malloc((size_t)(ny + 6) * sizeof(double));
+            fill_line(phi + i, nx, ny, p->bc_y, ext);
+            line_derivatives(ext, ny, p->dy, vm + i, nx, vp + i, nx);
+            free(ext);
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Hamiltonians of the test problems, H(u, v) with u = phi_x, v = phi_y:
+ *   LINEAR   a u + b v                    (Example 3.1)
+ *   BURGERS  (a u + b v + c)^2 / 2        (Examples 3.3, 3.6)
+ *   NEGCOS   -cos(a u + b v + c)          (Examples 3.2, 3.4)
+ *   NORM     s sqrt(u^2 + v^2 + k)        (Example 3.12 with k = 1; level-set motion with k = 0)
+ * hp = {a, b, c} or {s, k}.  In 1-D v is 0.
+ * ------------------------------------------------------------------------- */
+double orc_hamiltonian(const orc_problem *p, double u, double v)
+{
+    const double *h = p->hp;
+    switch (p->ham) {
+    case ORC_H_LINEAR:
+        return h[0] * u + h[1] * v;
+    case ORC_H_BURGERS: {
+        const double s = h[0] * u + h[1] * v + h[2];
+        return 0.5 * s * s;
+    }
+    case ORC_H_NEGCOS:
+        return -cos(h[0] * u + h[1] * v + h[2]);
+    case ORC_H_NORM:
+        return h[0] * sqrt(u * u + v * v + h[1]);
+    default:
+        return NAN;
+    }
+}
+
+/* max of |sin s| for s in [lo, hi] */
+static double max_abs_sin(double lo, double hi)
+{
+    const double pi = 3.14159265358979323846;
+    const double k = ceil((lo - 0.5 * pi) / pi); /* first pi/2 + k pi at or above lo */
+    if (0.5 * pi + k * pi <= hi)
+        return 1.0;
+    return fmax(fabs(sin(lo)), fabs(sin(hi)));
+}
+
+/* eq. (LF): alpha_x = max |H_1|, alpha_y = max |H_2| over the box [A,B] x [C,D]
+ * ([A,B] x {0} in 1-D). */
+void orc_dissipation(const orc_problem *p, double A, double B, double C, double D, double *ax,
+                     double *ay)
+{
+    const double *h = p->hp;
+    if (p->dim == 1) {
+        C = 0.0;
+        D = 0.0;
+    }
+    switch (p->ham) {
+    case ORC_H_LINEAR:
+        *ax = fabs(h[0]);
+        *ay = fabs(h[1]);
+        return;
+    case ORC_H_BURGERS:
+    case ORC_H_NEGCOS: {
+        /* s = a u + b v + c is linear: its extremes over the box are at corners */
+        const double s1 = h[0] * A + h[1] * C + h[2], s2 = h[0] * A + h[1] * D + h[2];
+        const double s3 = h[0] * B + h[1] * C + h[2], s4 = h[0] * B + h[1] * D + h[2];
+        const double lo = fmin(fmin(s1, s2), fmin(s3, s4));
+        const double hi = fmax(fmax(s1, s2), fmax(s3, s4));
+        /* H_1 = a H'(s), H_2 = b H'(s) with H'(s) = s or sin s */
+        const double m = (p->ham == ORC_H_BURGERS) ? fmax(fabs(lo), fabs(hi)) : max_abs_sin(lo, hi);
+        *ax = fabs(h[0]) * m;
+        *ay = fabs(h[1]) * m;
+        return;
+    }
+    case ORC_H_NORM: {
+        /* |H_1| = |s| |u| / sqrt(u^2+v^2+k): largest at the largest |u| and the smallest |v| */
+        const double U = fmax(fabs(A), fabs(B));
+        const double V = fmax(fabs(C), fabs(D));
+        const double umin = (A <= 0.0 && B >= 0.0) ? 0.0 : fmin(fabs(A), fabs(B));
+        const double vmin = (C <= 0.0 && D >= 0.0) ? 0.0 : fmin(fabs(C), fabs(D));
+        const double den_x = U * U + vmin * vmin + h[1];
+        const double den_y = V * V + umin * umin + h[1];
+        *ax = fabs(h[0]) * (den_x > 0.0 ? U / sqrt(den_x) : 1.0);
+        *ay = (p->dim == 2) ? fabs(h[0]) * (den_y > 0.0 ? V / sqrt(den_y) : 1.0) : 0.0;
+        return;
+    }
+    default:
+        *ax = NAN;
+        *ay = NAN;
+    }
+}
+
+/* eq. (LF), dimension by dimension */
+double orc_lax_friedrichs(const orc_problem *p, double um, double up, double vm, double vp,
+                          double ax, double ay)
+{
+    double H = orc_hamiltonian(p, 0.5 * (up + um), 0.5 * (vp + vm));
+    return H - ax * 0.5 * (up - um) - ay * 0.5 * (vp - vm);
+}
+
+/* L(phi) = -H_hat at every node, given alpha. */
+static int operator_L(const orc_problem *p, const double *phi, double ax, double ay, double *L,
+                      double *um, double *up, double *vm, double *vp)
+{
+    if (orc_derivatives(p, phi, um, up, vm, vp) != 0)
+        return -1;
+    const int64_t n = p->nx * p->ny;
+    for (int64_t k = 0; k < n; ++k) {
+        const double a = (p->dim == 2) ? vm[k] : 0.0, b = (p->dim == 2) ? vp[k] : 0.0;
+        L[k] = -orc_lax_friedrichs(p, um[k], up[k], a, b, ax, ay);
+    }
+    return 0;
+}
+
+/* Step 5: one TVD-RK3 step of phi (in place) from time t, with dt from the
+ * CFL rule clamped so that the step does not pass t_final.  Returns 0, -1 on
+ * bad arguments, -2 if a non-finite value appears. */
+int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, double cfl,
+                 orc_info *info)
+{
+    const int64_t n = p->nx * p->ny;
+    const size_t bytes = (size_t)n * sizeof(double);
+    double *um = malloc(bytes), *up = malloc(bytes), *vm = malloc(bytes), *vp = malloc(bytes);
+    double *L = malloc(bytes), *p0 = malloc(bytes), *p1 = malloc(bytes), *p2 = malloc(bytes);
+    int rc = 0;
+    if (!um || !up || !vm || !vp || !L || !p0 || !p1 || !p2) {
+        rc = -1;
+        goto out;
+    }
+    memcpy(p0, phi, bytes);
+
+    /* alpha from the derivative ranges of phi^n */
+    if (orc_derivatives(p, p0, um, up, vm, vp) != 0) {
+        rc = -1;
+        goto out;
+    }
+    double A = INFINITY, B = -INFINITY, C = 0.0, D = 0.0;
+    if (p->dim == 2) {
+        C = INFINITY;
+        D = -INFINITY;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        A = fmin(A, fmin(um[k], up[k]));
+        B = fmax(B, fmax(um[k], up[k]));
+        if (p->dim == 2) {
+            C = fmin(C, fmin(vm[k], vp[k]));
+            D = fmax(D, fmax(vm[k], vp[k]));
+        }
+    }
+    double ax, ay;
+    orc_dissipation(p, A, B, C, D, &ax, &ay);
+    const double rate = ax / p->dx + ((p->dim == 2) ? ay / p->dy : 0.0);
+    const double remaining = t_final - t;
+    double dt = (rate > 0.0) ? cfl / rate : remaining;
+    int last = 0;
+    if (!(dt < remaining)) {
+        dt = remaining;
+        last = 1;
+    }
+    if (!isfinite(dt) || !isfinite(ax) || !isfinite(ay)) {
+        rc = -2;
+        goto out;
+    }
+
+    /* phi_1 = phi_0 + dt L(phi_0) */
+    if (operator_L(p, p0, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
+    for (int64_t k = 0; k < n; ++k)
+        p1[k] = p0[k] + dt * L[k];
+    /* phi_2 = 3/4 phi_0 + 1/4 (phi_1 + dt L(phi_1)) */
+    if (operator_L(p, p1, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
+    for (int64_t k = 0; k < n; ++k)
+        p2[k] = 0.75 * p0[k] + 0.25 * (p1[k] + dt * L[k]);
+    /* phi^{n+1} = 1/3 phi_0 + 2/3 (phi_2 + dt L(phi_2)) */
+    if (operator_L(p, p2, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
+    for (int64_t k = 0; k < n; ++k) {
+        phi[k] = (1.0 / 3.0) * p0[k] + (2.0 / 3.0) * (p2[k] + dt * L[k]);
+        if (!isfinite(phi[k]))
+            rc = -2;
+    }
+    if (info) {
+        info->steps += 1;
+        info->t = last ? t_final : t + dt;
+        info->last_dt = dt;
+        info->alpha_x = ax;
+        info->alpha_y = ay;
+        info->range[0] = A;
+        info->range[1] = B;
+        info->range[2] = C;
+        info->range[3] = D;
+    }
+out:
+    free(um); free(up); free(vm); free(vp);
+    free(L); free(p0); free(p1); free(p2);
+    return rc;
+}
+
+/* Advance phi from info->t to t_final, at most max_steps steps (max_steps <= 0:
+ * no limit).  Returns 0, or the first non-zero code of orc_rk3_step. */
+int orc_step_to(const orc_problem *p, double *phi, double t_final, double cfl, int64_t max_steps,
+                orc_info *info)
+{
+    int64_t taken = 0;
+    while (info->t < t_final && (max_steps <= 0 || taken < max_steps)) {
+        const int rc = orc_rk3_step(p, phi, info->t, t_final, cfl, info);
+        if (rc)
+            return rc;
+        ++taken;
+    }
+    return 0;
+}

@@ -1,0 +1,450 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage of Rathan & Biswas (arXiv:1909.13263) it checks.
+None of them compares the oracle with itself: the references are exact rational
+arithmetic, adaptive quadrature, brute force from definitions (tests/brute_force.py),
+closed-form solutions (tests/exact_solutions.py), or the paper's printed tables.
+"""
+import math
+from fractions import Fraction
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import brute_force as BF
+import exact_solutions as E
+import oracle as O
+from conftest import load_table
+from paper_1909_13263_amd import workloads as W
+
+
+def _lagrange_derivative(nodes, values, x):
+    """Exact P'(x) of the interpolating polynomial through (nodes, values), in Fractions."""
+    total = Fraction(0)
+    n = len(nodes)
+    for j in range(n):
+        # d/dx of l_j(x) = sum_{m != j} prod_{k != j,m} (x - x_k) / prod_{k != j} (x_j - x_k)
+        den = Fraction(1)
+        for k in range(n):
+            if k != j:
+                den *= nodes[j] - nodes[k]
+        num = Fraction(0)
+        for m in range(n):
+            if m == j:
+                continue
+            prod = Fraction(1)
+            for k in range(n):
+                if k != j and k != m:
+                    prod *= x - nodes[k]
+            num += prod
+        total += values[j] * num / den
+    return total
+
+
+# --------------------------------------------------------------------------- Step 2
+def test_candidates_are_derivatives_of_substencil_cubics():
+    """Step 2: phi_{x,i}^{-,k} = p_{k,1}^-(x_i), the derivative at x_i of the cubic that
+    interpolates phi on {x_{i-3+k}, ..., x_{i+k}} (its cell averages of phi_x are the
+    Delta^+ phi of the sub-stencil)."""
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        ints = [int(z) for z in rng.integers(-50, 50, size=6)]
+        dx = Fraction(1, int(rng.integers(2, 9)))
+        xs = [k * dx for k in range(-3, 3)]          # x_{i-3..i+2}, x_i = 0
+        v = [float((ints[k + 1] - ints[k]) / dx) for k in range(5)]
+        q = O.candidates(v)
+        for k in range(3):
+            exact = _lagrange_derivative(xs[k:k + 4], [Fraction(z) for z in ints[k:k + 4]],
+                                         Fraction(0))
+            assert abs(q[k] - float(exact)) <= 1e-13 * max(1.0, abs(float(exact)))
+
+
+def test_linear_weights_reproduce_fifth_order_rows():
+    """Step 3 with Step 1: sum_k d_k phi^{-,k} gives the fifth-order row of phi_x^-.  The
+    printed row has -9/20 on Delta^+ phi_i; exactness on linear data (coefficients summing to 1)
+    requires +9/20.  The mirrored row is the phi_x^+ formula with +1/30 on Delta^+ phi_{i+2}."""
+    d = np.array([0.1, 0.6, 0.3])
+    Q = np.stack([O.candidates(np.eye(5)[j]) for j in range(5)], axis=1)   # 3 x 5
+    row = d @ Q
+    expect = np.array([1 / 30, -13 / 60, 47 / 60, 9 / 20, -1 / 20])
+    assert np.allclose(row, expect, rtol=0, atol=1e-15)
+    printed_minus = np.array([1 / 30, -13 / 60, 47 / 60, -9 / 20, -1 / 20])
+    printed_plus = np.array([-1 / 20, 9 / 20, 47 / 60, -13 / 60, -1 / 30])
+    assert abs(printed_minus.sum() - 0.1) < 1e-15 and abs(printed_plus.sum() - 14 / 15) < 1e-15
+    assert abs(row.sum() - 1.0) < 1e-15
+    assert np.allclose(row[::-1], [-1 / 20, 9 / 20, 47 / 60, -13 / 60, 1 / 30], atol=1e-15)
+
+
+# --------------------------------------------------------------------------- Step 4
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_arc_length_matches_quadrature(seed):
+    """eq. (length): L = int sqrt(1 + (b + 2 c x)^2) dx, against adaptive quadrature,
+    including c = 0, tiny c and large slopes (where the printed primitive cancels)."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(seed)
+    cases = [(0.3, 0.0, -0.1, 0.0), (1e6, 1e-9, -1e-3, 0.0), (-2.0, 1e-13, 0.0, 0.05),
+             (5.0, -3.0, -0.2, 0.1)]
+    for _ in range(40):
+        b = float(rng.normal() * 10 ** rng.uniform(-3, 5))
+        c = float(rng.normal() * 10 ** rng.uniform(-12, 6))
+        lo = float(rng.uniform(-1, 0))
+        hi = lo + float(10 ** rng.uniform(-4, 0))
+        cases.append((b, c, lo, hi))
+    for b, c, lo, hi in cases:
+        got = O.arc_length(b, c, lo, hi)
+        B, C = mp.mpf(b), mp.mpf(c)
+        s0, s1 = B + 2 * C * mp.mpf(lo), B + 2 * C * mp.mpf(hi)
+        pts = [mp.mpf(lo), mp.mpf(hi)]
+        if s0 * s1 < 0:   # split at the zero of the slope
+            pts = [pts[0], -B / (2 * C), pts[1]]
+        ref = mp.quad(lambda x: mp.sqrt(1 + (B + 2 * C * x) ** 2), pts)
+        assert abs(got - float(ref)) <= 2e-15 * float(ref), (b, c, lo, hi)
+
+
+def test_arc_length_special_cases():
+    """A straight segment (c = 0) has length dx sqrt(1+b^2); every length is >= dx."""
+    for b in [0.0, 1e-8, -3.0, 1e4]:
+        assert O.arc_length(b, 0.0, -0.01, 0.0) == pytest.approx(0.01 * math.sqrt(1 + b * b),
+                                                               rel=2e-16)
+    rng = np.random.default_rng(3)
+    for _ in range(100):
+        b, c = rng.normal(size=2) * 100
+        assert O.arc_length(b, c, -0.02, 0.0) >= 0.02 * (1 - 1e-15)
+
+
+def _grids_8():
+    rng = np.random.default_rng(7)
+    x = np.arange(8) / 8.0
+    return {
+        "random": rng.normal(size=8),
+        "smooth": np.sin(2 * math.pi * x) + 0.25 * np.cos(4 * math.pi * x),
+        "kink": np.abs(x - 0.5) * 3.0 + 0.1 * rng.normal(size=8),
+        "large": 40.0 * rng.normal(size=8),
+    }
+
+
+@pytest.mark.parametrize("case", ["random", "smooth", "kink", "large"])
+def test_one_sided_derivatives_match_brute_force(case):
+    """Steps 2-4 on an 8-point periodic grid: phi_x^-, phi_x^+, beta_k and omega_k against
+    brute force (Lagrange cubics, quadrature, the weight formula (WLOC1))."""
+    mp.mp.dps = 30
+    phi = _grids_8()[case]
+    dx = 0.125
+    prob = O.Problem((8,), (dx,), O.H_LINEAR, (1.0, 0.0))
+    um, up = O.derivatives(prob, phi)
+    for i in range(8):
+        bm = BF.one_sided(phi, i, dx, -1)
+        bp = BF.one_sided(phi, i, dx, +1)
+        scale = max(1.0, float(max(abs(z) for z in bm[3] + bp[3])))
+        assert abs(um[i] - float(bm[0])) <= 1e-13 * scale, (case, i)
+        assert abs(up[i] - float(bp[0])) <= 1e-13 * scale, (case, i)
+        # indicators and weights of the individual windows
+        f = np.array([phi[(i + k) % 8] for k in range(-3, 3)])
+        g = np.array([phi[(i + k) % 8] for k in range(-2, 4)])
+        _, beta_m, om_m = O.weno_l_minus(f, dx)
+        _, beta_p, om_p = O.weno_l_plus(g, dx)
+        for k in range(3):
+            assert beta_m[k] == pytest.approx(float(bm[1][k]), rel=1e-13)
+            assert om_m[k] == pytest.approx(float(bm[2][k]), rel=1e-12, abs=1e-15)
+            # the reflected ordering of the right-biased windows runs right to left
+            assert beta_p[k] == pytest.approx(float(bp[1][2 - k]), rel=1e-13)
+            assert om_p[k] == pytest.approx(float(bp[2][2 - k]), rel=1e-12, abs=1e-15)
+
+
+def test_rk3_step_matches_brute_force_2d():
+    """One whole TVD-RK3 step (Step 5) of Example 3.3's equation on an 8x8 periodic grid,
+    with Lax-Friedrichs flux (LF) and the global dissipation, against brute force."""
+    mp.mp.dps = 20
+    rng = np.random.default_rng(11)
+    n = 8
+    h = 0.5
+    x = np.arange(n) * h
+    phi = (np.sin(2 * math.pi * x / 4)[None, :] * np.cos(2 * math.pi * x / 4)[:, None]
+           + 0.3 * rng.normal(size=(n, n)))
+    prob = O.Problem((n, n), (h, h), O.H_BURGERS, (1.0, 1.0, 1.0))
+    got, info = O.rk3_step(prob, phi, 0.0, 10.0, 0.5)
+    ref, dt, alpha = BF.rk3_step_2d_burgers(phi.tolist(), h, h, 10.0, 0.5)
+    assert info.last_dt == pytest.approx(float(dt), rel=1e-14)
+    assert info.alpha_x == pytest.approx(float(alpha), rel=1e-14)
+    ref = np.array([[float(z) for z in r] for r in ref])
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_cubic_data_collapses_to_linear_weights():
+    """All three sub-stencil cubics coincide on cubic data, so the indicators are equal and
+    omega_k = d_k (Step 3); the derivative is then exact."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        c = rng.normal(size=4)
+        dx = float(10 ** rng.uniform(-3, -1))
+        x0 = float(rng.uniform(-1, 1))
+        f = lambda x: c[0] + c[1] * x + c[2] * x * x + c[3] * x ** 3
+        fp = lambda x: c[1] + 2 * c[2] * x + 3 * c[3] * x * x
+        xs = x0 + dx * np.arange(-3, 4)
+        vals = f(xs)
+        u, beta, om = O.weno_l_minus(vals[0:6], dx)
+        assert np.allclose(om, [0.1, 0.6, 0.3], rtol=0, atol=1e-9)
+        assert u == pytest.approx(fp(x0), abs=1e-8 * (1 + abs(fp(x0))) / dx * 1e-3 + 1e-9)
+        u, beta, om = O.weno_l_plus(vals[1:7], dx)
+        assert np.allclose(om, [0.1, 0.6, 0.3], rtol=0, atol=1e-9)
+        assert u == pytest.approx(fp(x0), abs=1e-8 * (1 + abs(fp(x0))) / dx * 1e-3 + 1e-9)
+
+
+def test_weights_approach_linear_weights_at_second_order():
+    """The Taylor expansion after (newbeta): omega_k = d_k + O(dx^2)."""
+    errs = []
+    hs = [0.1, 0.05, 0.025, 0.0125]
+    for h in hs:
+        worst = 0.0
+        for x0 in np.linspace(0.1, 3.0, 12):
+            xs = x0 + h * np.arange(-3, 3)
+            _, _, om = O.weno_l_minus(np.sin(xs) + 0.5 * np.cos(2 * xs), h)
+            worst = max(worst, float(np.max(np.abs(om - [0.1, 0.6, 0.3]))))
+        errs.append(worst)
+    slopes = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert all(1.8 < s < 2.2 for s in slopes), slopes
+
+
+def test_derivatives_converge_at_fifth_order():
+    """Step 1: the reconstruction is fifth order on smooth data."""
+    errs = []
+    for n in [40, 80, 160, 320]:
+        x = -1 + np.arange(n) * 2 / n
+        phi = np.sin(math.pi * x) + 0.3 * np.cos(2 * math.pi * x)
+        ex = math.pi * np.cos(math.pi * x) - 0.6 * math.pi * np.sin(2 * math.pi * x)
+        um, up = O.derivatives(O.Problem((n,), (2 / n,), O.H_LINEAR, (1.0, 0.0)), phi)
+        errs.append(max(np.abs(um - ex).max(), np.abs(up - ex).max()))
+    slopes = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert all(4.8 < s < 5.3 for s in slopes), slopes
+
+
+# --------------------------------------------------------------------------- flux and dissipation
+HAMS = [(O.H_LINEAR, (1.5, -0.5)), (O.H_BURGERS, (1.0, 1.0, 1.0)), (O.H_NEGCOS, (1.0, 1.0, 1.0)),
+        (O.H_NORM, (1.0, 0.0)), (O.H_NORM, (2.0, 1.0))]
+
+
+@pytest.mark.parametrize("ham,params", HAMS)
+def test_lax_friedrichs_consistent_and_monotone(ham, params):
+    """(LF) is consistent, H_hat(u,u) = H(u), and monotone (non-increasing in u+,
+    non-decreasing in u-) when alpha bounds |H_1| on the box."""
+    prob = O.Problem((8, 8), (0.1, 0.1), ham, params)
+    rng = np.random.default_rng(ham)
+    for _ in range(50):
+        u, v = rng.uniform(-2, 2, size=2)
+        assert O.lax_friedrichs(prob, u, u, v, v, 3.0, 3.0) == pytest.approx(
+            O.hamiltonian(prob, u, v), rel=1e-15, abs=1e-15)
+    A, B, C, D = -1.3, 0.7, -0.4, 1.1
+    ax, ay = O.dissipation(prob, A, B, C, D)
+    us = np.linspace(A, B, 9)
+    vs = np.linspace(C, D, 9)
+    h = 1e-4
+    for um in us:
+        for up in us:
+            for vm in vs[::4]:
+                for vp in vs[::4]:
+                    f = lambda a, b, c, d: O.lax_friedrichs(prob, a, b, c, d, ax, ay)
+                    if A <= up + h <= B:
+                        assert f(um, up + h, vm, vp) <= f(um, up, vm, vp) + 1e-12
+                    if A <= um + h <= B:
+                        assert f(um + h, up, vm, vp) >= f(um, up, vm, vp) - 1e-12
+                    if C <= vp + h <= D:
+                        assert f(um, up, vm, vp + h) <= f(um, up, vm, vp) + 1e-12
+                    if C <= vm + h <= D:
+                        assert f(um, up, vm + h, vp) >= f(um, up, vm, vp) - 1e-12
+
+
+@pytest.mark.parametrize("ham,params", HAMS)
+def test_dissipation_is_box_maximum(ham, params):
+    """alpha = max |H_1| (eq. LF), read as the maximum over the box of the step's derivative
+    ranges: against dense sampling of the box with central differences of H."""
+    prob = O.Problem((8, 8), (0.1, 0.1), ham, params)
+    rng = np.random.default_rng(100 + ham)
+    h = 1e-6
+    for trial in range(12):
+        if trial == 0:
+            A, B, C, D = -0.5, 0.5, -0.25, 0.75      # contains the origin
+        else:
+            A, B = np.sort(rng.uniform(-3, 3, size=2))
+            C, D = np.sort(rng.uniform(-3, 3, size=2))
+        ax, ay = O.dissipation(prob, A, B, C, D)
+        U = np.linspace(A, B, 161)
+        V = np.linspace(C, D, 161)
+        mx = my = 0.0
+        for u in U:
+            for v in V[::4]:
+                if abs(u) < 2 * h and abs(v) < 2 * h:
+                    continue
+                gx = (O.hamiltonian(prob, u + h, v) - O.hamiltonian(prob, u - h, v)) / (2 * h)
+                mx = max(mx, abs(gx))
+        for v in V:
+            for u in U[::4]:
+                if abs(u) < 2 * h and abs(v) < 2 * h:
+                    continue
+                gy = (O.hamiltonian(prob, u, v + h) - O.hamiltonian(prob, u, v - h)) / (2 * h)
+                my = max(my, abs(gy))
+        assert ax >= mx - 1e-6 and ay >= my - 1e-6
+        assert ax <= mx * (1 + 2e-2) + 1e-6 and ay <= my * (1 + 2e-2) + 1e-6, (A, B, C, D)
+
+
+# --------------------------------------------------------------------------- whole solver
+def _table_errors(make, ns, tf, exact, dims):
+    out = []
+    for n in ns:
+        pr = make(n, tf)
+        h = pr.spacing
+        prob = O.Problem(pr.shape, h, pr.ham, pr.params, pr.bc)
+        # dt proportional to dx^(5/3) so that the time error is of fifth order in dx
+        phi, info = O.step_to(prob, pr.phi0(), tf, 0.6 * h[0] ** (2.0 / 3.0))
+        assert info.t == tf
+        ex = exact(*[pr.coords(a) for a in range(dims)], tf)
+        e = np.abs(phi - ex)
+        vol = float(np.prod(h))
+        out.append((float(e.max()), float(vol * e.sum()), float(e.mean())))
+    return out
+
+
+def test_example31_table1():
+    """Example 3.1 / Table 1: linear advection to t = 2 (exact solution -cos(pi(x-t)))."""
+    tab = load_table("table1_example31.txt")
+    ns = [int(r[0]) for r in tab]
+    errs = _table_errors(W.advect1d, ns, 2.0, E.advect_1d, 1)
+    for k, (linf, l1, _) in enumerate(errs):
+        tol = 1.5 if ns[k] == 20 else 1.35
+        assert tab[k, 1] / tol <= linf <= tab[k, 1] * tol, (ns[k], linf)
+        # Table 1's L1 is the domain integral dx * sum |e|
+        assert tab[k, 3] / tol <= l1 <= tab[k, 3] * tol, (ns[k], l1)
+        if k >= 2:
+            order = math.log2(errs[k - 1][0] / linf)
+            assert abs(order - tab[k, 2]) < 0.15
+
+
+def test_example32_table2():
+    """Example 3.2 / Table 2: phi_t - cos(phi_x+1) = 0 to t = 0.5/pi^2.  The orders follow
+    the table; the magnitudes come out about 4.5x the printed ones (while Tables 1, 3 and 4
+    agree to within 35%), so only a loose magnitude band is asserted."""
+    tab = load_table("table2_example32.txt")
+    ns = [int(r[0]) for r in tab]
+    errs = _table_errors(W.negcos1d, ns, 0.5 / math.pi**2, E.negcos_1d, 1)
+    for k, (linf, l1, _) in enumerate(errs):
+        assert tab[k, 1] / 6 <= linf <= tab[k, 1] * 6, (ns[k], linf)
+        if k >= 2:
+            order = math.log2(errs[k - 1][0] / linf)
+            assert abs(order - tab[k, 2]) < 0.4, (ns[k], order)
+
+
+@pytest.mark.parametrize("make,exact,name", [(W.burgers2d, E.burgers_2d, "table3_example33.txt"),
+                                             (W.negcos2d, E.negcos_2d, "table4_example34.txt")])
+def test_examples33_34_tables3_4(make, exact, name):
+    """Examples 3.3 and 3.4 / Tables 3 and 4 on N x N grids, N = 20..160.  The 2-D L1 of the
+    tables matches the mean of |e| over the grid points."""
+    tab = load_table(name)
+    ns = [int(r[0]) for r in tab][:4]
+    errs = _table_errors(make, ns, 0.5 / math.pi**2, exact, 2)
+    for k, (linf, _, mean) in enumerate(errs):
+        tol = 1.5 if ns[k] >= 40 else 2.0
+        assert tab[k, 1] / tol <= linf <= tab[k, 1] * tol, (ns[k], linf)
+        assert tab[k, 3] / 2.0 <= mean <= tab[k, 3] * 2.0, (ns[k], mean)
+
+
+def test_config1_burgers1d_against_characteristics():
+    """Example 3.6's equation on N=160 with CFL 0.5 (dt proportional to dx) to t = 0.5/pi^2,
+    smooth regime: close to the exact solution; at fixed CFL the third-order time error
+    dominates."""
+    pr = W.burgers1d(160)
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params)
+    phi, info = O.step_to(prob, pr.phi0(), pr.t_final, 0.5)
+    assert info.t == pr.t_final
+    e = np.abs(phi - E.burgers_1d(pr.coords(0), pr.t_final)).max()
+    assert e < 2e-6, e
+
+
+def test_rk3_is_third_order_in_time():
+    """Step 5: the TVD-RK3 error falls as dt^3 (linear advection on a fine grid, where the
+    spatial error is far below the time error)."""
+    n = 640
+    pr = W.advect1d(n, 0.5)
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params)
+    errs = []
+    for cfl in [1.2, 0.6, 0.3]:
+        phi, _ = O.step_to(prob, pr.phi0(), 0.5, cfl)
+        errs.append(np.abs(phi - E.advect_1d(pr.coords(0), 0.5)).max())
+    slopes = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert all(2.8 < s < 3.2 for s in slopes), (errs, slopes)
+
+
+# --------------------------------------------------------------------------- symmetries, boundaries
+def test_transpose_symmetry_is_exact():
+    """Dimension by dimension (the Note after Step 5): transposing phi swaps (u, v) exactly,
+    and with a symmetric Hamiltonian a whole step commutes with the transpose."""
+    phi = W.random_smooth_periodic((24, 24), seed=3) + 0.05 * np.random.default_rng(3).normal(
+        size=(24, 24))
+    prob = O.Problem((24, 24), (0.1, 0.1), O.H_BURGERS, (1.0, 1.0, 1.0))
+    um, up, vm, vp = O.derivatives(prob, phi)
+    tm, tp, sm, sp = O.derivatives(prob, np.ascontiguousarray(phi.T))
+    assert np.array_equal(tm, vm.T) and np.array_equal(tp, vp.T)
+    assert np.array_equal(sm, um.T) and np.array_equal(sp, up.T)
+    a, _ = O.rk3_step(prob, phi, 0.0, 1.0, 0.5)
+    b, _ = O.rk3_step(prob, np.ascontiguousarray(phi.T), 0.0, 1.0, 0.5)
+    # the flux sums its x and y dissipation terms in a fixed order: equal up to rounding
+    assert np.allclose(a, b.T, rtol=0, atol=1e-14 * np.abs(a).max())
+
+
+def test_reflection_symmetry():
+    """Reflecting x -> -x maps phi_x^- to -phi_x^+ (Step 2, symmetric procedure), and the
+    solution of H(p) reflects to the solution of H(-p)."""
+    n = 32
+    phi = W.random_smooth_periodic((n,), seed=4) + 0.1 * np.abs(np.linspace(-1, 1, n))
+    ref = np.roll(phi[::-1], 1)          # phi~_i = phi_{-i}
+    prob = O.Problem((n,), (0.1,), O.H_BURGERS, (1.0, 0.0, 1.0))
+    um, up = O.derivatives(prob, phi)
+    rm, rp = O.derivatives(prob, ref)
+    assert np.allclose(rm, -np.roll(up[::-1], 1), rtol=0, atol=1e-13)
+    assert np.allclose(rp, -np.roll(um[::-1], 1), rtol=0, atol=1e-13)
+    mirror = O.Problem((n,), (0.1,), O.H_BURGERS, (-1.0, 0.0, 1.0))
+    a, _ = O.step_to(prob, phi, 0.05, 0.5)
+    b, _ = O.step_to(mirror, ref, 0.05, 0.5)
+    assert np.allclose(np.roll(b[::-1], 1), a, rtol=0, atol=1e-12)
+
+
+def test_extrapolated_boundary_is_exact_on_linear_data():
+    """Linear extrapolation into the ghosts keeps linear data linear, so every one-sided
+    derivative, at the boundary too, equals the slope."""
+    ny, nx = 12, 16
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    phi = 3.0 * x[None, :] - 2.0 * y[:, None] + 1.0
+    prob = O.Problem((ny, nx), (1 / nx, 1 / ny), O.H_NORM, (1.0, 0.0), O.BC_EXTRAP)
+    um, up, vm, vp = O.derivatives(prob, phi)
+    for a, val in [(um, 3.0), (up, 3.0), (vm, -2.0), (vp, -2.0)]:
+        assert np.allclose(a, val, rtol=0, atol=1e-11)
+
+
+def test_levelset_circles_against_hopf_lax():
+    """Level-set motion phi_t + |grad phi| = 0 from the union-of-circles phi0 (extrapolated
+    boundaries) against the closed form min_k(max(|x-c_k|-t, 0) - r_k): the solution has kinks,
+    so the error is bounded by the mesh width, falls under refinement, and the sign of phi
+    (inside/outside of the front) is right wherever the exact |phi| exceeds 3 dx."""
+    c, r = W.circles(W.CIRCLE_SEED)
+    means = []
+    for n in (64, 128):
+        pr = W.levelset2d(n, 0.05)
+        prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc)
+        phi, info = O.step_to(prob, pr.phi0(), pr.t_final, 0.5)
+        ex = E.levelset_circles(pr.coords(0), pr.coords(1), pr.t_final, c, r)
+        e = np.abs(phi - ex)
+        h = pr.spacing[0]
+        assert e.max() < 1.8 * h
+        far = np.abs(ex) > 3 * h
+        assert np.array_equal(np.sign(phi[far]), np.sign(ex[far]))
+        means.append(e.mean())
+    assert means[1] < 0.15 * (1 / 128) and means[0] / means[1] > 2.0, means
+
+
+def test_non_finite_input_is_reported():
+    pr = W.burgers1d(32)
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params)
+    phi = pr.phi0()
+    phi[5] = np.nan
+    with pytest.raises(FloatingPointError):
+        O.step_to(prob, phi, 0.01, 0.5)
