@@ -1,0 +1,209 @@
+"""Benchmark: cell-updates/s per RK3 stage of the WENO-L solver on one MI355X.
+
+One benchmark step is one whole solve of the 2-D Burgers problem of Example 3.3 scaled
+to a 1024 x 1024 periodic grid on [-2,2)^2, phi0 = -cos(pi(x+y)/2), CFL 0.5, from t = 0
+to t = 0.5/pi^2: every RK3 step (derivative ranges -> dissipation -> time step -> three
+fused stages) runs on the GPU, from phi0 already resident in HBM.
+
+value = cells x RK stages / wall time for the FP32-stencil path (FP64 phi, FP64 time step
+and accumulation); the FP64 path is timed the same way and reported beside it.  The
+roofline object describes the dominant kernel, timed with HIP events on the library's
+stream during an instrumented solve that follows the timed region.  cpu_baseline is the
+FP64 oracle on the host cores, on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E, 8 TB/s
+# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39,322 G lane-slots/s
+# (one lane-operation per lane per clock, packed FP32 not used).
+VALU_PEAK_GSLOTS = 256 * 4 * 16 * 2.4
+# Algorithmic vector work of one node-stage in 2-D: about 200 add/mul/FMA plus 28
+# square roots, logarithms, divisions and reciprocals (6 + 6 + 12 + 4), the latter at
+# quarter rate (4 slots each): 200 + 28 * 4 = 312 lane-slots.
+ALGO_SLOTS_PER_CELL = 200 + 28 * 4
+METRIC = "cell-updates/s per RK3 stage (FP32 vs FP64, %HBM peak); served p50/p99 latency"
+
+# Compulsory HBM bytes per node of each kernel of a step (read stage inputs once, write
+# outputs once): [pre, finalize, mid, last] for (phi bytes, flux bytes).
+def kernel_bytes_per_cell(phi_b, flux_b):
+    return {
+        "pre": phi_b + 3 * flux_b,                 # read phi^n; write Hbar, Dx, Dy
+        "finalize": 0.0,
+        "mid": phi_b + 3 * flux_b + phi_b,         # read phi^n, Hbar, Dx, Dy; write phi_2
+        "last": 2 * phi_b + phi_b,                 # read phi^n, phi_2; write phi^{n+1}
+    }
+
+
+# HBM bytes per launch of the FP32-stencil kernels at 1024 x 1024 from rocprofv3 counters
+# (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors a 256 MiB copy kernel reads for its known
+# bytes); None when the kernel changed after the counters were taken.
+MEASURED_TRAFFIC = {}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for 256 MiB."""
+    import torch
+    n = 256 * 1024 * 1024
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}))
+    return 0
+
+
+def time_solves(hjw, pr, prec, phi_dev, steps, warmup):
+    import torch
+    g = hjw.grid_for(pr, prec)
+    info = None
+    for _ in range(warmup):
+        g.set_phi(phi_dev)
+        info = g.step_to(pr.t_final, pr.cfl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.set_phi(phi_dev)
+        info = g.step_to(pr.t_final, pr.cfl)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # instrumented solve: every kernel bracketed by HIP events on the library's stream
+    g.set_option(hjw.OPT_KERNEL_EVENTS, 1)
+    g.set_phi(phi_dev)
+    g.step_to(pr.t_final, pr.cfl)
+    times = g.kernel_times()
+    g.set_option(hjw.OPT_KERNEL_EVENTS, 0)
+    g.close()
+    return wall, info, times
+
+
+def cpu_baseline(pr, seconds):
+    """The FP64 oracle on the host: whole RK3 steps of the same grid until `seconds` pass."""
+    import oracle as O
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc)
+    phi = pr.phi0()
+    steps = 0
+    t = 0.0
+    t0 = time.perf_counter()
+    while True:
+        phi, info = O.rk3_step(prob, phi, t, pr.t_final, pr.cfl)
+        t = info.t
+        steps += 1
+        if time.perf_counter() - t0 >= seconds or t >= pr.t_final:
+            break
+    wall = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pr.cells * 3 * steps / wall, "unit": "cell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{steps} RK3 steps of the {pr.shape[1]}x{pr.shape[0]} grid from t=0 "
+                      f"({wall:.1f} s, FP64 C, OpenMP over grid lines)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver runs each grid on a single device).", file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_1909_13263_amd import hjw
+    from paper_1909_13263_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        return calibrate_copy()
+    pr = W.burgers2d(args.n, 0.5 / math.pi**2)
+    phi_dev = torch.from_numpy(pr.phi0()).to("cuda")
+    cells = pr.cells
+
+    results = {}
+    for name, prec in [("fp32", hjw.FP32_MIXED), ("fp64", hjw.FP64)]:
+        if name == "fp64" and args.skip_fp64:
+            continue
+        wall, info, times = time_solves(hjw, pr, prec, phi_dev, args.steps, args.warmup)
+        stages = 3 * info.steps
+        results[name] = {"wall": wall, "rk_steps": info.steps, "stages": stages,
+                         "cell_updates_per_s": cells * stages * args.steps / wall,
+                         "ms_per_solve": 1e3 * wall / args.steps, "kernels": times}
+
+    main_res = results["fp32"]
+    # dominant kernel of the FP32-stencil path
+    ktimes = main_res["kernels"]
+    dom = max(("pre", "mid", "last"), key=lambda k: ktimes[k][0])
+    dom_ms = ktimes[dom][0] / max(1, ktimes[dom][1])
+    bpc = kernel_bytes_per_cell(8, 4)[dom]
+    hbm_gbs = bpc * cells / (dom_ms * 1e-3) / 1e9
+    alu_achieved = ALGO_SLOTS_PER_CELL * cells / (dom_ms * 1e-3) / 1e9
+    traffic = MEASURED_TRAFFIC.get((args.n, dom))
+    # whole-step compulsory bytes per cell-stage: (8 + 8+8 + 8+8 ... ) averaged over stages
+    step_bytes = sum(kernel_bytes_per_cell(8, 4).values())
+    sustained = step_bytes * cells * main_res["rk_steps"] * args.steps / main_res["wall"] / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": main_res["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 stencil, f64 phi/dt/accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"burgers2d {args.n}x{args.n} periodic [-2,2)^2, "
+                               "phi0=-cos(pi(x+y)/2), H=(p+q+1)^2/2, LF, TVD-RK3, CFL 0.5, "
+                               "t=0.5/pi^2",
+                   "cells": cells, "rk_steps": main_res["rk_steps"],
+                   "stages_per_solve": main_res["stages"]},
+        "roofline": {"bound": "alu", "kernel": f"k_stage2d<float,double,{dom}>",
+                     "achieved": alu_achieved, "peak": VALU_PEAK_GSLOTS,
+                     "unit": "G lane-slots/s", "frac": alu_achieved / VALU_PEAK_GSLOTS,
+                     "traffic": traffic, "avg_launch_ms": dom_ms,
+                     "algorithmic_slots_per_cell": ALGO_SLOTS_PER_CELL},
+        "hbm": {"kernel_GBps": hbm_gbs, "kernel_frac": hbm_gbs / HBM_PEAK_GBS,
+                "sustained_GBps": sustained, "sustained_frac": sustained / HBM_PEAK_GBS,
+                "peak_GBps": HBM_PEAK_GBS},
+        "kernel_ms": {k: (v[0] / max(1, v[1])) for k, v in ktimes.items()},
+    }
+    if "fp64" in results:
+        r = results["fp64"]
+        line["fp64"] = {"value": r["cell_updates_per_s"], "ms_per_step": r["ms_per_solve"],
+                        "rk_steps": r["rk_steps"],
+                        "kernel_ms": {k: (v[0] / max(1, v[1])) for k, v in r["kernels"].items()}}
+        line["fp32_speedup_over_fp64"] = main_res["cell_updates_per_s"] / r["cell_updates_per_s"]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,144 @@
+/*
+ * hjw.h - C ABI of the MI355X WENO-L Hamilton-Jacobi library.
+ *
+ * Solves phi_t + H(D phi) = 0, phi(x,0) = phi0(x), on a uniform 1-D or 2-D grid
+ * (Rathan & Biswas, arXiv:1909.13263, eq. (HJ) restricted to Hamiltonians that
+ * depend on D phi only) with the fifth-order arc-length WENO derivatives of
+ * Section 2 (Steps 1-4), the Lax-Friedrichs numerical Hamiltonian (eq. LF) and
+ * third-order TVD Runge-Kutta in time (Step 5); two dimensions are handled
+ * dimension by dimension (the Note closing Section 2).
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns an hjw_status; nothing throws or aborts across the ABI.
+ *     hjw_last_error() returns a thread-local message for the last failure.
+ *   - Arrays are row-major with x fastest: phi[j*nx + i] = phi(x_i, y_j).  phi is
+ *     exchanged as FP64 in every precision mode.
+ *   - A periodic axis of n points covers [lo, hi) with x_i = lo + i*h, h = (hi-lo)/n;
+ *     an extrapolated axis is cell-centred, x_i = lo + (i+1/2)*h.  n >= 8 per axis.
+ *   - The library owns hjw_grid objects.  The caller owns every pointer it passes:
+ *     host arrays, device arrays and the device workspace given to hjw_bind, which
+ *     must stay allocated until hjw_grid_destroy.
+ *   - One grid is not thread-safe; distinct grids may be used from distinct threads.
+ *   - After a non-finite value is detected a grid is failed: every call except
+ *     hjw_set_phi, hjw_get_info and hjw_grid_destroy returns HJW_ESTATE.
+ */
+#ifndef HJW_H
+#define HJW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HJW_OK = 0,
+    HJW_EINVAL = -1,     /* bad argument or unsupported combination            */
+    HJW_ENOMEM = -2,     /* workspace too small / host allocation failed        */
+    HJW_EHIP = -3,       /* a HIP runtime call failed (message has the code)     */
+    HJW_ESTATE = -4,     /* call not valid in the grid's state (unbound, failed) */
+    HJW_ENONFINITE = -5, /* a non-finite derivative, flux or phi appeared        */
+    HJW_EBUSY = -6       /* resource in use                                      */
+} hjw_status;
+
+typedef enum { HJW_BC_PERIODIC = 0, HJW_BC_EXTRAP = 1 } hjw_bc;
+
+/* Arithmetic of the stencil (candidates, indicators, weights, flux):
+ *   HJW_FP64        everything in FP64;
+ *   HJW_FP32_MIXED  stencil in FP32 on differences taken in FP64; phi stored and
+ *                   accumulated in FP64; dissipation and time step in FP64;
+ *   HJW_FP32        as FP32_MIXED but phi stored in FP32 (RK combination still
+ *                   evaluated in FP64 before rounding). */
+typedef enum { HJW_FP64 = 0, HJW_FP32_MIXED = 1, HJW_FP32 = 2 } hjw_prec;
+
+/* Built-in Hamiltonians H(u, v), u = phi_x, v = phi_y (v = 0 in 1-D):
+ *   LINEAR   p[0]*u + p[1]*v                    (Example 3.1)
+ *   BURGERS  (p[0]*u + p[1]*v + p[2])^2 / 2     (Examples 3.3, 3.6)
+ *   NEGCOS   -cos(p[0]*u + p[1]*v + p[2])       (Examples 3.2, 3.4)
+ *   NORM     p[0]*sqrt(u^2 + v^2 + p[1])        (Example 3.12 with p[1] = 1;
+ *                                                level-set motion with p[1] = 0) */
+typedef enum { HJW_H_LINEAR = 0, HJW_H_BURGERS = 1, HJW_H_NEGCOS = 2, HJW_H_NORM = 3 } hjw_ham;
+
+/* Options for hjw_set_option. */
+typedef enum {
+    HJW_OPT_USE_GRAPH = 0,     /* 1 (default): replay captured HIP graphs of whole RK steps;
+                                  0: launch every kernel eagerly.  Results are identical. */
+    HJW_OPT_KERNEL_EVENTS = 1  /* 1: launch eagerly and bracket every kernel of a step with
+                                  HIP events on the grid's stream; resets the totals that
+                                  hjw_kernel_times reports.  0 (default): off. */
+} hjw_option;
+
+typedef struct hjw_grid hjw_grid;
+
+typedef struct {
+    int64_t steps;    /* RK3 steps taken since the last hjw_set_phi                  */
+    double t;         /* current time                                               */
+    double last_dt;   /* time step of the last step                                 */
+    double alpha_x;   /* dissipation of the last step, max |H_1| over the box (LF)  */
+    double alpha_y;
+    double range[4];  /* the box: min/max of phi_x^-, phi_x^+ and of phi_y^-, phi_y^+ */
+} hjw_info;
+
+/* Create a grid.  dim = 1 or 2; n[d], lo[d], hi[d], bc[d] per axis, x first.
+ * Nothing is allocated on the device.  *out receives the grid. */
+hjw_status hjw_grid_create(int dim, const int64_t *n, const double *lo, const double *hi,
+                           const int *bc, int prec, hjw_grid **out);
+
+/* Bytes of device workspace the grid needs (its whole HBM footprint: phi, the
+ * stage buffer, the three stage-1 flux arrays, block partials and the step state). */
+hjw_status hjw_workspace_bytes(const hjw_grid *g, size_t *bytes);
+
+/* Bind device memory (>= hjw_workspace_bytes, 256-byte aligned) and a HIP stream
+ * (hipStream_t; NULL lets the library create its own blocking stream).  The
+ * workspace and stream are borrowed.  Rebinding is allowed; phi must be set again. */
+hjw_status hjw_bind(hjw_grid *g, void *dev_workspace, size_t bytes, void *hip_stream);
+
+/* Choose the Hamiltonian (see hjw_ham) and its parameters (nparams <= 4). */
+hjw_status hjw_set_hamiltonian(hjw_grid *g, int kind, const double *params, int nparams);
+
+/* Copy phi0 (FP64, nx*ny values, host or device memory) into the grid; t := 0,
+ * steps := 0, the failed state is cleared.  Synchronous. */
+hjw_status hjw_set_phi(hjw_grid *g, const double *phi0, int on_device);
+
+/* Advance with TVD-RK3 until t = t_final or max_steps steps were taken
+ * (max_steps <= 0: no limit).  dt = cfl / (alpha_x/dx + alpha_y/dy), clamped so
+ * that the last step lands on t_final exactly.  Blocking; fills *info if not NULL.
+ * Returns HJW_ENONFINITE (and fails the grid) if a non-finite value appears. */
+hjw_status hjw_step_to(hjw_grid *g, double t_final, double cfl, int64_t max_steps,
+                       hjw_info *info);
+
+/* Copy phi (FP64, nx*ny values) out to host or device memory.  Synchronous. */
+hjw_status hjw_get_phi(const hjw_grid *g, double *out, int on_device);
+
+/* The fifth-order WENO-L one-sided derivatives of the current phi (Steps 1-4):
+ * phi_x^-, phi_x^+ and, in 2-D, phi_y^-, phi_y^+ (vm, vp ignored in 1-D), written
+ * as FP64 to caller-owned device arrays of nx*ny values.  Synchronous. */
+hjw_status hjw_derivatives(hjw_grid *g, double *um, double *up, double *vm, double *vp);
+
+/* Current step counters and last step's dissipation/time step. */
+hjw_status hjw_get_info(const hjw_grid *g, hjw_info *info);
+
+hjw_status hjw_set_option(hjw_grid *g, int option, int64_t value);
+
+/* With HJW_OPT_KERNEL_EVENTS on: total milliseconds and launch counts of the four
+ * kernels of a step since the option was switched on, in the order
+ * [0] derivatives of phi^n and block ranges, [1] dissipation and time step,
+ * [2] second stage, [3] third stage.  ms[4] and count[4] are caller-owned. */
+hjw_status hjw_kernel_times(const hjw_grid *g, double *ms, int64_t *count);
+
+/* Release the grid (its graphs, events and own stream); the workspace is the
+ * caller's.  NULL is ignored. */
+void hjw_grid_destroy(hjw_grid *g);
+
+/* Thread-local description of the last error ("" if none). */
+const char *hjw_last_error(void);
+
+/* Library version string. */
+const char *hjw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJW_H */

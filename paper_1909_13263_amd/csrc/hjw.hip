@@ -1,0 +1,818 @@
+// hjw.hip - HIP kernels for gfx950 and the C ABI declared in include/hjw.h.
+//
+// One TVD-RK3 step (Rathan & Biswas, arXiv:1909.13263, Step 5) is four launches:
+//   k_stage<Pre>   WENO-L derivatives of phi^n (Steps 1-4), writes Hbar = H(ubar,vbar),
+//                  Dx = (u+ - u-)/2, Dy = (v+ - v-)/2 and per-block min/max of u+-, v+-;
+//   k_finalize     one workgroup: the ranges -> alpha_x, alpha_y (eq. LF, maximum of
+//                  |H_p| over the box) -> dt (CFL rule) -> step state;
+//   k_stage<Mid>   rebuilds phi_1 = phi^n - dt (Hbar - ax Dx - ay Dy) on the tile and
+//                  its halo, derivatives of phi_1, phi_2 = 3/4 phi^n + 1/4 (phi_1 + dt L);
+//   k_stage<Last>  derivatives of phi_2, phi^{n+1} = 1/3 phi^n + 2/3 (phi_2 + dt L),
+//                  written in place over phi^n.
+// The step state lives on the device, so whole steps are captured once in a HIP
+// graph and replayed; kernels of a step past t_final exit at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hjw.h"
+#include "hjw_tile.h"
+
+using namespace hjw;
+
+namespace {
+
+// Tile shapes: 64 x 32 nodes per workgroup in 2-D (segments of 8 per thread),
+// 1024 nodes in 1-D (segments of 4).
+constexpr int kTX = 64, kTY = 32, kSX = 8, kSY = 8;
+constexpr int kTX1 = 1024, kS1 = 4;
+constexpr int kGraphSteps = 16;
+constexpr int kMaxBatch = 512;  // steps enqueued between two reads of the step state
+
+thread_local std::string g_last_error;
+
+hjw_status fail(hjw_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(HJW_EHIP, "%s failed: %s (%d)", #expr, hipGetErrorString(e_),     \
+                        int(e_));                                                         \
+    } while (0)
+
+// ------------------------------------------------------------------ kernels
+template <typename T>
+__device__ inline T wave_min(T x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+    return x;
+}
+template <typename T>
+__device__ inline T wave_max(T x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+
+__device__ inline bool step_open(const DevState* st) {
+    return st->bad == 0 && st->t < st->t_final && st->steps_left > 0;
+}
+
+__device__ inline int tile_of_block(int bid, int nb, int remap) {
+    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of
+    // tiles so that tile halos are shared through that XCD's L2.
+    return remap ? (bid % 8) * (nb / 8) + bid / 8 : bid;
+}
+
+template <int NW, typename T, typename P>
+__device__ inline void write_partials(const StageArgs<T, P>& a, T lu, T hu, T lv, T hv, bool bad,
+                                      int bid) {
+    __shared__ double red[NW][4];
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    lu = wave_min(lu);
+    hu = wave_max(hu);
+    lv = wave_min(lv);
+    hv = wave_max(hv);
+    const int anybad = __syncthreads_or(bad ? 1 : 0);
+    if (lane == 0) {
+        red[w][0] = double(lu);
+        red[w][1] = double(hu);
+        red[w][2] = double(lv);
+        red[w][3] = double(hv);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r0 = red[0][0], r1 = red[0][1], r2 = red[0][2], r3 = red[0][3];
+        for (int k = 1; k < NW; ++k) {
+            r0 = fmin(r0, red[k][0]);
+            r1 = fmax(r1, red[k][1]);
+            r2 = fmin(r2, red[k][2]);
+            r3 = fmax(r3, red[k][3]);
+        }
+        double* p = a.partials + size_t(bid) * kPartialStride;
+        p[0] = r0;
+        p[1] = r1;
+        p[2] = r2;
+        p[3] = r3;
+        p[4] = anybad ? 1.0 : 0.0;
+    }
+}
+
+// Reduce all workgroups' partials and plan the step (256 threads of one workgroup).
+__device__ void plan_from_partials(const double* partials, int nb, DevState* st, int kind,
+                                   const double* p, int dim, double ihx, double ihy) {
+    __shared__ double red[4][5];
+    double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY, bad = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const double* q = partials + size_t(b) * kPartialStride;
+        lu = fmin(lu, q[0]);
+        hu = fmax(hu, q[1]);
+        lv = fmin(lv, q[2]);
+        hv = fmax(hv, q[3]);
+        bad = fmax(bad, q[4]);
+    }
+    lu = wave_min(lu);
+    hu = wave_max(hu);
+    lv = wave_min(lv);
+    hv = wave_max(hv);
+    bad = wave_max(bad);
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    if (lane == 0) {
+        red[w][0] = lu;
+        red[w][1] = hu;
+        red[w][2] = lv;
+        red[w][3] = hv;
+        red[w][4] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[4] = {red[0][0], red[0][1], red[0][2], red[0][3]};
+        double b = red[0][4];
+        for (int k = 1; k < 4; ++k) {
+            r[0] = fmin(r[0], red[k][0]);
+            r[1] = fmax(r[1], red[k][1]);
+            r[2] = fmin(r[2], red[k][2]);
+            r[3] = fmax(r[3], red[k][3]);
+            b = fmax(b, red[k][4]);
+        }
+        DevState s = *st;
+        s.active = 0;
+        if (b != 0.0 || !(finite_t(r[0]) && finite_t(r[1]) && finite_t(r[2]) && finite_t(r[3]))) {
+            s.bad = 1;
+        } else {
+            plan_step(s, kind, p, dim, ihx, ihy, r);
+            s.active = s.bad ? 0 : 1;
+        }
+        *st = s;
+    }
+}
+
+template <typename T, typename P, int STAGE>
+__global__ __launch_bounds__(512) void k_stage2d(StageArgs<T, P> a) {
+    using TL = Tile<T, P, kTX, kTY, kSX, kSY>;
+    __shared__ P phiL[TL::kPhiElems];
+    __shared__ T uL[TL::kUElems];
+    double dt = 0.0, ax = 0.0, ay = 0.0;
+    if (STAGE == kStagePre) {
+        if (!step_open(a.st)) return;
+    } else if (STAGE == kStageMid || STAGE == kStageLast) {
+        if (!a.st->active) return;
+        dt = a.st->dt;
+        ax = a.st->alpha_x;
+        ay = a.st->alpha_y;
+    }
+    const int nb = a.nbx * a.nby;
+    const int tile = tile_of_block(blockIdx.x, nb, a.remap);
+    const int64_t x0 = int64_t(tile % a.nbx) * kTX;
+    const int64_t y0 = int64_t(tile / a.nbx) * kTY;
+    const int tid = threadIdx.x;
+
+    TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL);
+    __syncthreads();
+    T vm[kSY], vp[kSY];
+    const bool rows = tid < TL::kHalf;   // wave-uniform: waves 0-3 rows, 4-7 columns
+    if (rows)
+        TL::sweep_x(tid, a, phiL, uL);
+    else
+        TL::sweep_y(tid - TL::kHalf, a, phiL, vm, vp);
+    __syncthreads();
+    Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
+    if (!rows) TL::finish(tid - TL::kHalf, uL, vm, vp, fin);
+
+    if (STAGE == kStagePre) {
+        write_partials<8>(a, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad, blockIdx.x);
+    } else if (STAGE == kStageLast) {
+        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st->bad = 1;
+    }
+}
+
+template <typename T, typename P, int STAGE>
+__global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
+    using TL = Tile1D<T, P, kTX1, kS1>;
+    __shared__ P phiL[TL::kPhiElems];
+    __shared__ T uL[TL::kUElems];
+    double dt = 0.0, ax = 0.0;
+    if (STAGE == kStagePre) {
+        if (!step_open(a.st)) return;
+    } else if (STAGE == kStageMid || STAGE == kStageLast) {
+        if (!a.st->active) return;
+        dt = a.st->dt;
+        ax = a.st->alpha_x;
+    }
+    const int64_t x0 = int64_t(blockIdx.x) * kTX1;
+    const int tid = threadIdx.x;
+    TL::template load<STAGE>(tid, a, x0, dt, ax, 0.0, phiL);
+    __syncthreads();
+    TL::sweep_x(tid, a, phiL, uL);
+    __syncthreads();
+    Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
+    for (int c = tid; c < kTX1; c += 256) fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0));
+    if (STAGE == kStagePre) {
+        write_partials<4>(a, fin.lo_u, fin.hi_u, T(0), T(0), fin.bad, blockIdx.x);
+    } else if (STAGE == kStageLast) {
+        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st->bad = 1;
+    }
+}
+
+// One workgroup: the ranges of phi^n's derivatives -> dissipation -> time step.
+__global__ __launch_bounds__(256) void k_finalize(const double* partials, int nb, DevState* st,
+                                                  int kind, double p0, double p1, double p2,
+                                                  double p3, int dim, double ihx, double ihy) {
+    __shared__ int s_open;
+    if (threadIdx.x == 0) s_open = step_open(st) ? 1 : 0;
+    __syncthreads();
+    if (!s_open) {
+        if (threadIdx.x == 0) st->active = 0;
+        return;
+    }
+    const double p[4] = {p0, p1, p2, p3};
+    plan_from_partials(partials, nb, st, kind, p, dim, ihx, ihy);
+}
+
+__global__ void k_set_target(DevState* st, double t_final, double cfl, int64_t steps_left) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->t_final = t_final;
+        st->cfl = cfl;
+        st->steps_left = steps_left;
+        st->active = 0;
+    }
+}
+
+__global__ void k_reset(DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        DevState s;
+        s.t = 0.0;
+        s.t_final = 0.0;
+        s.cfl = 0.0;
+        s.dt = 0.0;
+        s.alpha_x = 0.0;
+        s.alpha_y = 0.0;
+        for (int k = 0; k < 4; ++k) s.range[k] = 0.0;
+        s.steps = 0;
+        s.steps_left = 0;
+        s.active = 0;
+        s.bad = 0;
+        s.pad[0] = s.pad[1] = 0;
+        *st = s;
+    }
+}
+
+__global__ void k_d2f(const double* in, float* out, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = float(in[i]);
+}
+
+__global__ void k_f2d(const float* in, double* out, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = double(in[i]);
+}
+
+__global__ void k_check_finite(const double* in, int64_t n, DevState* st) {
+    int bad = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        if (!finite_t(in[i])) bad = 1;
+    if (__syncthreads_or(bad) && threadIdx.x == 0) st->bad = 1;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ the grid object
+struct hjw_grid {
+    int dim = 0;
+    int64_t nx = 0, ny = 1;
+    double dx = 0.0, dy = 1.0;
+    int bcx = 0, bcy = 0;
+    int prec = 0;
+    int ham = kHBurgers;
+    double hp[4] = {1.0, 1.0, 1.0, 0.0};
+    bool ham_set = false;
+
+    // binding
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool bound = false;
+    void* phi = nullptr;
+    void* phi2 = nullptr;
+    void* flux = nullptr;  // Hbar, Dx, Dy back to back
+    double* partials = nullptr;
+    DevState* state = nullptr;
+    int nbx = 0, nby = 0;
+
+    // host mirror
+    DevState* pinned = nullptr;  // pinned host copy of the device state
+    bool phi_set = false;
+    bool failed = false;
+    DevState last{};
+
+    // graphs
+    bool use_graph = true;
+    bool graph_ok = false;
+    hipGraphExec_t graph = nullptr;
+
+    // per-kernel event timing (eager launches only)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;       // start/end pairs
+    std::vector<int> ev_kind;
+    int ev_used = 0;
+    double kernel_ms[4] = {0, 0, 0, 0};
+    int64_t kernel_count[4] = {0, 0, 0, 0};
+
+    size_t elem_phi() const { return prec == HJW_FP32 ? 4 : 8; }
+    size_t elem_flux() const { return prec == HJW_FP64 ? 8 : 4; }
+    int64_t cells() const { return nx * ny; }
+};
+
+namespace {
+
+void layout(const hjw_grid* g, size_t* off_phi2, size_t* off_flux, size_t* off_part,
+            size_t* off_state, size_t* total, int* nbx, int* nby) {
+    const size_t n = size_t(g->cells());
+    if (g->dim == 2) {
+        *nbx = int((g->nx + kTX - 1) / kTX);
+        *nby = int((g->ny + kTY - 1) / kTY);
+    } else {
+        *nbx = int((g->nx + kTX1 - 1) / kTX1);
+        *nby = 1;
+    }
+    const size_t nb = size_t(*nbx) * size_t(*nby);
+    size_t o = 0;
+    o += align256(n * g->elem_phi());
+    *off_phi2 = o;
+    o += align256(n * g->elem_phi());
+    *off_flux = o;
+    // three flux arrays, and at least 8n bytes (an FP64 staging area in FP32 mode)
+    o += align256(std::max(size_t(3) * n * g->elem_flux(), n * 8));
+    *off_part = o;
+    o += align256(nb * kPartialStride * sizeof(double));
+    *off_state = o;
+    o += align256(sizeof(DevState));
+    *total = o;
+}
+
+template <typename T, typename P>
+StageArgs<T, P> make_args(const hjw_grid* g) {
+    StageArgs<T, P> a{};
+    const size_t n = size_t(g->cells());
+    a.phi_n = static_cast<const P*>(g->phi);
+    a.phi_s = static_cast<const P*>(g->phi2);
+    a.hbar = static_cast<T*>(g->flux);
+    a.dxa = a.hbar + n;
+    a.dya = a.hbar + 2 * n;
+    a.partials = g->partials;
+    a.st = g->state;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.bcx = g->bcx;
+    a.bcy = g->bcy;
+    a.ihx = P(1.0 / g->dx);
+    a.ihy = P(1.0 / g->dy);
+    a.ihxT = T(1.0 / g->dx);
+    a.ihyT = T(1.0 / g->dy);
+    a.epsx = T(kEps / (g->dx * g->dx));
+    a.epsy = T(kEps / (g->dy * g->dy));
+    a.ham = g->ham;
+    for (int k = 0; k < 4; ++k) {
+        a.hpT[k] = T(g->hp[k]);
+        a.hpD[k] = g->hp[k];
+    }
+    a.ihxD = 1.0 / g->dx;
+    a.ihyD = g->dim == 2 ? 1.0 / g->dy : 0.0;
+    a.nbx = g->nbx;
+    a.nby = g->nby;
+    a.remap = (g->dim == 2 && (g->nbx * g->nby) % 8 == 0) ? 1 : 0;
+    a.dim = g->dim;
+    return a;
+}
+
+template <typename T, typename P, int STAGE>
+hipError_t launch_stage(const hjw_grid* g, StageArgs<T, P> a) {
+    const dim3 grid(unsigned(g->nbx * g->nby));
+    if (g->dim == 2)
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE>), grid, dim3(512), 0, g->stream, a);
+    else
+        hipLaunchKernelGGL((k_stage1d<T, P, STAGE>), grid, dim3(256), 0, g->stream, a);
+    return hipGetLastError();
+}
+
+// Launch one kernel through fn(); with timing on, bracket it by a pair of events.
+template <class Fn>
+hipError_t timed(hjw_grid* g, int kind, Fn fn) {
+    if (!g->timing) return fn();
+    if (size_t(2 * g->ev_used + 2) > g->ev.size()) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(g->ev[2 * g->ev_used], g->stream);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(g->ev[2 * g->ev_used + 1], g->stream);
+    if (e != hipSuccess) return e;
+    g->ev_kind[g->ev_used++] = kind;
+    return hipSuccess;
+}
+
+template <typename T, typename P>
+hipError_t enqueue_step_typed(hjw_grid* g) {
+    StageArgs<T, P> a = make_args<T, P>(g);
+    hipError_t e = timed(g, 0, [&] { return launch_stage<T, P, kStagePre>(g, a); });
+    if (e != hipSuccess) return e;
+    e = timed(g, 1, [&] {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, g->stream, g->partials,
+                           g->nbx * g->nby, g->state, g->ham, g->hp[0], g->hp[1], g->hp[2],
+                           g->hp[3], g->dim, a.ihxD, a.ihyD);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    a.out = static_cast<P*>(g->phi2);
+    e = timed(g, 2, [&] { return launch_stage<T, P, kStageMid>(g, a); });
+    if (e != hipSuccess) return e;
+    a.out = static_cast<P*>(g->phi);
+    return timed(g, 3, [&] { return launch_stage<T, P, kStageLast>(g, a); });
+}
+
+hipError_t enqueue_step(hjw_grid* g) {
+    switch (g->prec) {
+    case HJW_FP64:
+        return enqueue_step_typed<double, double>(g);
+    case HJW_FP32_MIXED:
+        return enqueue_step_typed<float, double>(g);
+    default:
+        return enqueue_step_typed<float, float>(g);
+    }
+}
+
+template <typename T, typename P>
+hipError_t enqueue_deriv_typed(const hjw_grid* g, double* um, double* up, double* vm,
+                               double* vp) {
+    StageArgs<T, P> a = make_args<T, P>(g);
+    a.dout0 = um;
+    a.dout1 = up;
+    a.dout2 = vm;
+    a.dout3 = vp;
+    return launch_stage<T, P, kStageDeriv>(g, a);
+}
+
+void drop_graph(hjw_grid* g) {
+    if (g->graph) (void)hipGraphExecDestroy(g->graph);
+    g->graph = nullptr;
+    g->graph_ok = false;
+}
+
+hjw_status build_graph(hjw_grid* g) {
+    drop_graph(g);
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = enqueue_step(g);
+    hipError_t e2 = hipStreamEndCapture(g->stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(HJW_EHIP, "graph capture failed: %s / %s", hipGetErrorString(e),
+                    hipGetErrorString(e2));
+    }
+    hipError_t e3 = hipGraphInstantiate(&g->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+        g->graph = nullptr;
+        return fail(HJW_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+    }
+    g->graph_ok = true;
+    return HJW_OK;
+}
+
+hjw_status enqueue_steps(hjw_grid* g, int64_t n) {
+    if (g->use_graph && !g->timing && n >= kGraphSteps) {
+        if (!g->graph_ok) {
+            hjw_status s = build_graph(g);
+            if (s != HJW_OK) return s;
+        }
+        while (n >= kGraphSteps) {
+            HIP_TRY(hipGraphLaunch(g->graph, g->stream));
+            n -= kGraphSteps;
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) HIP_TRY(enqueue_step(g));
+    return HJW_OK;
+}
+
+hjw_status read_state(hjw_grid* g) {
+    HIP_TRY(hipMemcpyAsync(g->pinned, g->state, sizeof(DevState), hipMemcpyDeviceToHost,
+                           g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->last = *g->pinned;
+    for (int k = 0; k < g->ev_used; ++k) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]));
+        g->kernel_ms[g->ev_kind[k]] += ms;
+        g->kernel_count[g->ev_kind[k]] += 1;
+    }
+    g->ev_used = 0;
+    return HJW_OK;
+}
+
+void fill_info(const hjw_grid* g, hjw_info* info) {
+    if (!info) return;
+    info->steps = g->last.steps;
+    info->t = g->last.t;
+    info->last_dt = g->last.dt;
+    info->alpha_x = g->last.alpha_x;
+    info->alpha_y = g->last.alpha_y;
+    for (int k = 0; k < 4; ++k) info->range[k] = g->last.range[k];
+}
+
+hjw_status check_ready(const hjw_grid* g) {
+    if (!g) return fail(HJW_EINVAL, "grid is NULL");
+    if (!g->bound) return fail(HJW_ESTATE, "grid has no workspace bound");
+    if (g->failed) return fail(HJW_ESTATE, "grid failed (non-finite values); set phi again");
+    return HJW_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* hjw_last_error(void) { return g_last_error.c_str(); }
+
+const char* hjw_version(void) { return "hjw 0.1 (WENO-L, gfx950)"; }
+
+hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const double* hi,
+                           const int* bc, int prec, hjw_grid** out) {
+    g_last_error.clear();
+    if (!out) return fail(HJW_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dim != 1 && dim != 2) return fail(HJW_EINVAL, "dim must be 1 or 2 (got %d)", dim);
+    if (!n || !lo || !hi || !bc) return fail(HJW_EINVAL, "NULL array argument");
+    if (prec < HJW_FP64 || prec > HJW_FP32) return fail(HJW_EINVAL, "unknown precision %d", prec);
+    for (int d = 0; d < dim; ++d) {
+        if (n[d] < 8) return fail(HJW_EINVAL, "n[%d] = %lld < 8", d, (long long)n[d]);
+        if (!(hi[d] > lo[d]) || !std::isfinite(lo[d]) || !std::isfinite(hi[d]))
+            return fail(HJW_EINVAL, "axis %d: need finite lo < hi", d);
+        if (bc[d] != HJW_BC_PERIODIC && bc[d] != HJW_BC_EXTRAP)
+            return fail(HJW_EINVAL, "axis %d: unknown boundary %d", d, bc[d]);
+    }
+    if (n[0] > (int64_t(1) << 30) || (dim == 2 && n[1] > (int64_t(1) << 30)) ||
+        (dim == 2 && n[0] * n[1] > (int64_t(1) << 34)))
+        return fail(HJW_EINVAL, "grid too large");
+    hjw_grid* g = new (std::nothrow) hjw_grid();
+    if (!g) return fail(HJW_ENOMEM, "host allocation failed");
+    g->dim = dim;
+    g->nx = n[0];
+    g->ny = dim == 2 ? n[1] : 1;
+    g->dx = (hi[0] - lo[0]) / double(n[0]);
+    g->dy = dim == 2 ? (hi[1] - lo[1]) / double(n[1]) : 1.0;
+    g->bcx = bc[0];
+    g->bcy = dim == 2 ? bc[1] : HJW_BC_PERIODIC;
+    g->prec = prec;
+    if (dim == 2 && int64_t(g->nx + kTX - 1) / kTX * ((g->ny + kTY - 1) / kTY) > INT32_MAX) {
+        delete g;
+        return fail(HJW_EINVAL, "too many tiles");
+    }
+    *out = g;
+    return HJW_OK;
+}
+
+hjw_status hjw_workspace_bytes(const hjw_grid* g, size_t* bytes) {
+    if (!g || !bytes) return fail(HJW_EINVAL, "NULL argument");
+    size_t a, b, c, d, total;
+    int nbx, nby;
+    layout(g, &a, &b, &c, &d, &total, &nbx, &nby);
+    *bytes = total;
+    return HJW_OK;
+}
+
+hjw_status hjw_bind(hjw_grid* g, void* ws, size_t bytes, void* stream) {
+    if (!g || !ws) return fail(HJW_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(HJW_EINVAL, "workspace must be 256-byte aligned");
+    size_t o_phi2, o_flux, o_part, o_state, total;
+    int nbx, nby;
+    layout(g, &o_phi2, &o_flux, &o_part, &o_state, &total, &nbx, &nby);
+    if (bytes < total)
+        return fail(HJW_ENOMEM, "workspace has %zu bytes, grid needs %zu", bytes, total);
+    drop_graph(g);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    g->own_stream = false;
+    g->stream = static_cast<hipStream_t>(stream);
+    if (!g->stream) {
+        HIP_TRY(hipStreamCreate(&g->stream));
+        g->own_stream = true;
+    }
+    if (!g->pinned) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g->pinned), sizeof(DevState),
+                                          hipHostMallocDefault));
+    g->ws = static_cast<char*>(ws);
+    g->ws_bytes = bytes;
+    g->phi = g->ws;
+    g->phi2 = g->ws + o_phi2;
+    g->flux = g->ws + o_flux;
+    g->partials = reinterpret_cast<double*>(g->ws + o_part);
+    g->state = reinterpret_cast<DevState*>(g->ws + o_state);
+    g->nbx = nbx;
+    g->nby = nby;
+    g->bound = true;
+    g->phi_set = false;
+    g->failed = false;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g->stream, g->state);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->last = DevState{};
+    return HJW_OK;
+}
+
+hjw_status hjw_set_hamiltonian(hjw_grid* g, int kind, const double* params, int nparams) {
+    if (!g) return fail(HJW_EINVAL, "grid is NULL");
+    if (kind < HJW_H_LINEAR || kind > HJW_H_NORM)
+        return fail(HJW_EINVAL, "unknown Hamiltonian %d", kind);
+    if (nparams < 0 || nparams > 4 || (nparams > 0 && !params))
+        return fail(HJW_EINVAL, "bad parameter list");
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nparams; ++k) {
+        if (!std::isfinite(params[k])) return fail(HJW_EINVAL, "non-finite parameter");
+        p[k] = params[k];
+    }
+    if (kind == HJW_H_NORM && p[1] < 0.0) return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    g->ham = kind;
+    for (int k = 0; k < 4; ++k) g->hp[k] = p[k];
+    g->ham_set = true;
+    drop_graph(g);
+    return HJW_OK;
+}
+
+hjw_status hjw_set_phi(hjw_grid* g, const double* phi0, int on_device) {
+    if (!g || !phi0) return fail(HJW_EINVAL, "NULL argument");
+    if (!g->bound) return fail(HJW_ESTATE, "grid has no workspace bound");
+    const size_t n = size_t(g->cells());
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    // FP64 input lands in phi itself, or in the flux area when phi is FP32
+    double* src = g->prec == HJW_FP32 ? static_cast<double*>(g->flux) : static_cast<double*>(g->phi);
+    HIP_TRY(hipMemcpyAsync(src, phi0, n * sizeof(double), kind, g->stream));
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g->stream, g->state);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, g->stream, src, int64_t(n),
+                       g->state);
+    HIP_TRY(hipGetLastError());
+    if (g->prec == HJW_FP32) {
+        hipLaunchKernelGGL(k_d2f, dim3(1024), dim3(256), 0, g->stream, src,
+                           static_cast<float*>(g->phi), int64_t(n));
+        HIP_TRY(hipGetLastError());
+    }
+    hjw_status s = read_state(g);
+    if (s != HJW_OK) return s;
+    g->phi_set = true;
+    g->failed = false;
+    if (g->last.bad) {
+        g->failed = true;
+        return fail(HJW_ENONFINITE, "phi0 holds non-finite values");
+    }
+    return HJW_OK;
+}
+
+hjw_status hjw_step_to(hjw_grid* g, double t_final, double cfl, int64_t max_steps,
+                       hjw_info* info) {
+    hjw_status s = check_ready(g);
+    if (s != HJW_OK) return s;
+    if (!g->phi_set) return fail(HJW_ESTATE, "phi was not set");
+    if (!g->ham_set) return fail(HJW_ESTATE, "Hamiltonian was not set");
+    if (!std::isfinite(t_final) || !(cfl > 0.0) || !std::isfinite(cfl))
+        return fail(HJW_EINVAL, "need finite t_final and cfl > 0");
+    const int64_t limit = max_steps > 0 ? max_steps : std::numeric_limits<int64_t>::max();
+    hipLaunchKernelGGL(k_set_target, dim3(1), dim3(64), 0, g->stream, g->state, t_final, cfl,
+                       limit);
+    HIP_TRY(hipGetLastError());
+    s = read_state(g);
+    if (s != HJW_OK) return s;
+    int64_t taken = 0;
+    while (g->last.t < t_final && taken < limit && !g->last.bad) {
+        int64_t n = 1;
+        if (g->last.dt > 0.0) {
+            const double est = std::ceil((t_final - g->last.t) / g->last.dt);
+            n = est > 1.0 ? int64_t(std::min(est, double(kMaxBatch))) : 1;
+        }
+        n = std::min(n, limit - taken);
+        s = enqueue_steps(g, n);
+        if (s != HJW_OK) return s;
+        const int64_t before = g->last.steps;
+        s = read_state(g);
+        if (s != HJW_OK) return s;
+        taken += g->last.steps - before;
+        if (g->last.steps == before && !g->last.bad) break;  // nothing advanced
+    }
+    fill_info(g, info);
+    if (g->last.bad) {
+        g->failed = true;
+        return fail(HJW_ENONFINITE, "non-finite value at step %lld (t = %g)",
+                    (long long)g->last.steps, g->last.t);
+    }
+    return HJW_OK;
+}
+
+hjw_status hjw_get_phi(const hjw_grid* g, double* out, int on_device) {
+    if (!g || !out) return fail(HJW_EINVAL, "NULL argument");
+    if (!g->bound || !g->phi_set) return fail(HJW_ESTATE, "phi was not set");
+    const size_t n = size_t(g->cells());
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const void* src = g->phi;
+    if (g->prec == HJW_FP32) {
+        double* stage = static_cast<double*>(g->flux);
+        hipLaunchKernelGGL(k_f2d, dim3(1024), dim3(256), 0, g->stream,
+                           static_cast<const float*>(g->phi), stage, int64_t(n));
+        HIP_TRY(hipGetLastError());
+        src = stage;
+    }
+    HIP_TRY(hipMemcpyAsync(out, src, n * sizeof(double), kind, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return HJW_OK;
+}
+
+hjw_status hjw_derivatives(hjw_grid* g, double* um, double* up, double* vm, double* vp) {
+    hjw_status s = check_ready(g);
+    if (s != HJW_OK) return s;
+    if (!g->phi_set) return fail(HJW_ESTATE, "phi was not set");
+    if (!um || !up || (g->dim == 2 && (!vm || !vp))) return fail(HJW_EINVAL, "NULL output");
+    hipError_t e;
+    switch (g->prec) {
+    case HJW_FP64:
+        e = enqueue_deriv_typed<double, double>(g, um, up, vm, vp);
+        break;
+    case HJW_FP32_MIXED:
+        e = enqueue_deriv_typed<float, double>(g, um, up, vm, vp);
+        break;
+    default:
+        e = enqueue_deriv_typed<float, float>(g, um, up, vm, vp);
+    }
+    if (e != hipSuccess) return fail(HJW_EHIP, "derivative launch failed: %s", hipGetErrorString(e));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return HJW_OK;
+}
+
+hjw_status hjw_get_info(const hjw_grid* g, hjw_info* info) {
+    if (!g || !info) return fail(HJW_EINVAL, "NULL argument");
+    fill_info(g, info);
+    return HJW_OK;
+}
+
+hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
+    if (!g) return fail(HJW_EINVAL, "grid is NULL");
+    if (option == HJW_OPT_USE_GRAPH) {
+        g->use_graph = value != 0;
+        if (!g->use_graph) drop_graph(g);
+        return HJW_OK;
+    }
+    if (option == HJW_OPT_KERNEL_EVENTS) {
+        if (value != 0 && g->ev.empty()) {
+            g->ev.resize(size_t(8) * kMaxBatch, nullptr);
+            g->ev_kind.resize(size_t(4) * kMaxBatch, 0);
+            for (auto& e : g->ev) HIP_TRY(hipEventCreate(&e));
+        }
+        g->timing = value != 0;
+        g->ev_used = 0;
+        for (int k = 0; k < 4; ++k) {
+            g->kernel_ms[k] = 0.0;
+            g->kernel_count[k] = 0;
+        }
+        return HJW_OK;
+    }
+    return fail(HJW_EINVAL, "unknown option %d", option);
+}
+
+hjw_status hjw_kernel_times(const hjw_grid* g, double* ms, int64_t* count) {
+    if (!g || !ms || !count) return fail(HJW_EINVAL, "NULL argument");
+    for (int k = 0; k < 4; ++k) {
+        ms[k] = g->kernel_ms[k];
+        count[k] = g->kernel_count[k];
+    }
+    return HJW_OK;
+}
+
+void hjw_grid_destroy(hjw_grid* g) {
+    if (!g) return;
+    drop_graph(g);
+    for (auto& e : g->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+    if (g->pinned) (void)hipHostFree(g->pinned);
+    delete g;
+}
+
+}  // extern "C"

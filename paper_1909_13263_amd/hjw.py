@@ -1,0 +1,208 @@
+"""Thin ctypes binding of the C ABI in include/hjw.h.
+
+Argument marshalling only: every step of the scheme runs in the HIP library
+(libhjw.so).  PyTorch provides the device workspace; nothing here computes.
+Raises if the library was not built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhjw.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_EXTRAP = 0, 1
+FP64, FP32_MIXED, FP32 = 0, 1, 2
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM = 0, 1, 2, 3
+OPT_USE_GRAPH = 0
+OPT_KERNEL_EVENTS = 1
+KERNEL_NAMES = ("pre", "finalize", "mid", "last")
+
+PREC_NAMES = {"fp64": FP64, "fp32_mixed": FP32_MIXED, "fp32": FP32}
+
+
+class HJWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hjw error {code}: {msg}")
+        self.code = code
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("t", ctypes.c_double), ("last_dt", ctypes.c_double),
+                ("alpha_x", ctypes.c_double), ("alpha_y", ctypes.c_double),
+                ("range", ctypes.c_double * 4)]
+
+
+@dataclass
+class Info:
+    steps: int
+    t: float
+    last_dt: float
+    alpha_x: float
+    alpha_y: float
+    range: tuple
+
+
+_lib = None
+
+
+def lib():
+    """Load libhjw.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "hjw_grid_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(i64), dp, dp,
+                                               ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                               ctypes.POINTER(vp)]),
+            "hjw_workspace_bytes": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+            "hjw_bind": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+            "hjw_set_hamiltonian": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.c_int]),
+            "hjw_set_phi": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+            "hjw_step_to": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, i64,
+                                           ctypes.POINTER(_Info)]),
+            "hjw_get_phi": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+            "hjw_derivatives": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+            "hjw_get_info": (ctypes.c_int, [vp, ctypes.POINTER(_Info)]),
+            "hjw_set_option": (ctypes.c_int, [vp, ctypes.c_int, i64]),
+            "hjw_kernel_times": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
+            "hjw_grid_destroy": (None, [vp]),
+            "hjw_last_error": (ctypes.c_char_p, []),
+            "hjw_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != OK:
+        raise HJWError(code, lib().hjw_last_error().decode())
+
+
+def _info(ci: _Info) -> Info:
+    return Info(int(ci.steps), ci.t, ci.last_dt, ci.alpha_x, ci.alpha_y, tuple(ci.range))
+
+
+class Grid:
+    """One solve: a uniform grid, a Hamiltonian and phi, resident on the GPU.
+
+    shape is (nx,) or (ny, nx); lo, hi and bc are per axis, x first."""
+
+    def __init__(self, shape, lo, hi, bc=BC_PERIODIC, prec=FP64, stream=None, workspace=None):
+        import torch
+        L = lib()
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        n = self.shape[::-1]
+        bcs = bc if isinstance(bc, (tuple, list)) else (bc,) * self.dim
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
+        self.prec = prec
+        arr_n = (ctypes.c_int64 * self.dim)(*n)
+        arr_lo = (ctypes.c_double * self.dim)(*[float(v) for v in lo])
+        arr_hi = (ctypes.c_double * self.dim)(*[float(v) for v in hi])
+        arr_bc = (ctypes.c_int * self.dim)(*[int(b) for b in bcs])
+        h = ctypes.c_void_p()
+        _check(L.hjw_grid_create(self.dim, arr_n, arr_lo, arr_hi, arr_bc, int(prec),
+                                 ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(L.hjw_workspace_bytes(self._h, ctypes.byref(nb)))
+        self.workspace_bytes = int(nb.value)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+        self._ws = workspace
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(L.hjw_bind(self._h, ctypes.c_void_p(workspace.data_ptr()),
+                          ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(s)))
+
+    @property
+    def cells(self):
+        return int(np.prod(self.shape))
+
+    def set_hamiltonian(self, kind, params):
+        p = (ctypes.c_double * 4)(*([float(v) for v in params] + [0.0] * (4 - len(params))))
+        _check(lib().hjw_set_hamiltonian(self._h, int(kind), p, len(params)))
+
+    def set_phi(self, phi):
+        import torch
+        if isinstance(phi, torch.Tensor) and phi.is_cuda:
+            t = phi.detach().to(torch.float64).contiguous()
+            assert tuple(t.shape) == self.shape
+            torch.cuda.current_stream().synchronize()
+            _check(lib().hjw_set_phi(self._h, ctypes.c_void_p(t.data_ptr()), 1))
+        else:
+            a = np.ascontiguousarray(np.asarray(phi, dtype=np.float64))
+            assert a.shape == self.shape, (a.shape, self.shape)
+            _check(lib().hjw_set_phi(self._h, a.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def step_to(self, t_final, cfl=0.5, max_steps=0) -> Info:
+        ci = _Info()
+        _check(lib().hjw_step_to(self._h, float(t_final), float(cfl), int(max_steps),
+                                 ctypes.byref(ci)))
+        return _info(ci)
+
+    def info(self) -> Info:
+        ci = _Info()
+        _check(lib().hjw_get_info(self._h, ctypes.byref(ci)))
+        return _info(ci)
+
+    def get_phi(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        _check(lib().hjw_get_phi(self._h, out.ctypes.data_as(ctypes.c_void_p), 0))
+        return out
+
+    def get_phi_device(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        _check(lib().hjw_get_phi(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+        return out
+
+    def derivatives(self):
+        """(u-, u+) or (u-, u+, v-, v+) as FP64 CUDA tensors."""
+        import torch
+        outs = [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(4)]
+        ptrs = [ctypes.c_void_p(o.data_ptr()) for o in outs]
+        _check(lib().hjw_derivatives(self._h, *ptrs))
+        return tuple(outs[:2]) if self.dim == 1 else tuple(outs)
+
+    def set_option(self, option, value):
+        _check(lib().hjw_set_option(self._h, int(option), int(value)))
+
+    def kernel_times(self):
+        """{kernel: (total_ms, launches)} recorded with OPT_KERNEL_EVENTS on."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(lib().hjw_kernel_times(self._h, ms, cnt))
+        return {KERNEL_NAMES[k]: (ms[k], int(cnt[k])) for k in range(4)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hjw_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grid_for(problem, prec=FP64, **kw) -> Grid:
+    """A Grid for a workloads.Problem, with its Hamiltonian set."""
+    g = Grid(problem.shape, problem.lo, problem.hi, problem.bc, prec, **kw)
+    g.set_hamiltonian(problem.ham, problem.params)
+    return g

@@ -1,0 +1,79 @@
+"""The C ABI library loads, exports every entry point of include/hjw.h and validates
+arguments on the host (no GPU work: nothing here binds a workspace)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1909_13263_amd import hjw
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "hjw.h")).read()
+    return sorted(set(re.findall(r"\b(hjw_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_interface():
+    names = _declared()
+    for required in ["hjw_grid_create", "hjw_workspace_bytes", "hjw_bind", "hjw_set_hamiltonian",
+                     "hjw_set_phi", "hjw_step_to", "hjw_get_phi", "hjw_derivatives",
+                     "hjw_grid_destroy", "hjw_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = hjw.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _create(dim, n, lo, hi, bc, prec):
+    L = hjw.lib()
+    h = ctypes.c_void_p()
+    rc = L.hjw_grid_create(dim, (ctypes.c_int64 * len(n))(*n), (ctypes.c_double * len(lo))(*lo),
+                           (ctypes.c_double * len(hi))(*hi), (ctypes.c_int * len(bc))(*bc), prec,
+                           ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((3, [16, 16], [0, 0], [1, 1], [0, 0], 0), "dim"),
+    ((2, [7, 16], [0, 0], [1, 1], [0, 0], 0), "< 8"),
+    ((2, [16, 16], [1, 0], [1, 1], [0, 0], 0), "lo < hi"),
+    ((2, [16, 16], [0, 0], [1, 1], [0, 5], 0), "boundary"),
+    ((1, [16], [0], [1], [0], 7), "precision"),
+])
+def test_create_rejects_bad_arguments(args, msg):
+    rc, h = _create(*args)
+    assert rc == hjw.EINVAL
+    assert msg in hjw.lib().hjw_last_error().decode()
+    assert not h.value
+
+
+@pytest.mark.parametrize("prec,per_cell", [(hjw.FP64, 40), (hjw.FP32_MIXED, 28), (hjw.FP32, 20)])
+def test_workspace_is_the_hbm_footprint(prec, per_cell):
+    """phi + stage buffer + three flux arrays per cell, plus block partials and state."""
+    L = hjw.lib()
+    rc, h = _create(2, [1024, 1024], [-2, -2], [2, 2], [0, 0], prec)
+    assert rc == 0
+    nb = ctypes.c_size_t()
+    assert L.hjw_workspace_bytes(h, ctypes.byref(nb)) == 0
+    cells = 1024 * 1024
+    tiles = (1024 // 64) * (1024 // 32)
+    assert per_cell * cells <= nb.value <= per_cell * cells + tiles * 40 + 4096
+    L.hjw_grid_destroy(h)
+
+
+def test_calls_on_unbound_grid_fail_cleanly():
+    L = hjw.lib()
+    rc, h = _create(1, [160], [-1], [1], [0], hjw.FP64)
+    assert rc == 0
+    info = hjw._Info()
+    assert L.hjw_step_to(h, 1.0, 0.5, 0, ctypes.byref(info)) == hjw.ESTATE
+    assert L.hjw_set_hamiltonian(h, 9, None, 0) == hjw.EINVAL
+    assert L.hjw_set_option(h, 42, 1) == hjw.EINVAL
+    L.hjw_grid_destroy(h)
+    L.hjw_grid_destroy(None)

@@ -1,0 +1,73 @@
+"""The GPU tile code run on the CPU (libhjw_emu.so: the same phases of hjw_tile.h, with
+NaN-filled LDS and guard zones) against the oracle.  This checks the kernels' indexing
+(ragged tiles, halos, boundaries) and arithmetic before and independently of any GPU run."""
+import math
+
+import numpy as np
+import pytest
+
+import emulator as EM
+import oracle as O
+from paper_1909_13263_amd import workloads as W
+
+# FP64 must match to rounding; the FP32 stencil to single-precision rounding of the
+# derivative (relative to the largest derivative on the grid).
+TOL = {0: 1e-13, 1: 2e-6, 2: 2e-5}
+
+SHAPES = [(8,), (37,), (160,), (1030,), (8, 8), (33, 65), (40, 70), (64, 64), (96, 130)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_derivatives_match_oracle(shape, bc, prec):
+    rng = np.random.default_rng(len(shape) * 1000 + sum(shape))
+    phi = W.random_smooth_periodic(shape, seed=sum(shape)) + 0.05 * rng.normal(size=shape)
+    h = tuple(0.05 + 0.01 * a for a in range(len(shape)))
+    ref = O.derivatives(O.Problem(shape, h, O.H_LINEAR, (1.0, 0.0), bc), phi)
+    got = EM.derivatives(phi, h, bc, prec)
+    for g, r in zip(got, ref):
+        assert np.isfinite(g).all()
+        assert np.abs(g - r).max() <= TOL[prec] * np.abs(r).max()
+
+
+def _cases():
+    return [W.burgers1d(160), W.advect1d(37), W.negcos1d(50), W.burgers2d(96, ny=70),
+            W.negcos2d(65, ny=33), W.levelset2d(100, ny=72)]
+
+
+@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_rk3_step_matches_oracle(case, prec):
+    pr = _cases()[case]
+    phi = pr.phi0()
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc)
+    ref, info = O.rk3_step(prob, phi, 0.0, pr.t_final, 0.5)
+    rc, got, ei = EM.rk3_step(phi, pr.spacing, pr.ham, pr.params, 0.0, pr.t_final, 0.5, pr.bc,
+                              prec)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    assert np.abs(got - ref).max() <= {0: 1e-14, 1: 1e-7, 2: 1e-6}[prec] * np.abs(ref).max()
+
+
+def test_emulated_step_flags_non_finite():
+    pr = W.burgers2d(64)
+    phi = pr.phi0()
+    phi[10, 20] = math.inf
+    rc, _, info = EM.rk3_step(phi, pr.spacing, pr.ham, pr.params, 0.0, 0.01, 0.5, pr.bc, 0)
+    assert rc == -5 and info[8] == 1.0
+
+
+def test_emulated_transpose_is_bitwise():
+    """x and y go through the same sweep, so transposing phi swaps (u, v) exactly, and with
+    a symmetric Hamiltonian a whole step commutes with the transpose bit for bit."""
+    pr = W.burgers2d(96)
+    phi = pr.phi0() + 0.01 * W.random_smooth_periodic(pr.shape, seed=9)
+    u = EM.derivatives(phi, pr.spacing, 0, 0)
+    v = EM.derivatives(np.ascontiguousarray(phi.T), pr.spacing, 0, 0)
+    assert np.array_equal(u[0], v[2].T) and np.array_equal(u[1], v[3].T)
+    for prec in (0, 1):
+        _, a, _ = EM.rk3_step(phi, pr.spacing, pr.ham, pr.params, 0.0, 1.0, 0.5, 0, prec)
+        _, b, _ = EM.rk3_step(np.ascontiguousarray(phi.T), pr.spacing, pr.ham, pr.params, 0.0,
+                              1.0, 0.5, 0, prec)
+        assert np.array_equal(a, b.T)
