@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0, help="16 or 32 (0: library default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -78,9 +79,11 @@ def calibrate_copy():
     return 0
 
 
-def time_solves(hjw, pr, prec, phi_dev, steps, warmup):
+def time_solves(hjw, pr, prec, phi_dev, steps, warmup, tile_rows=0):
     import torch
     g = hjw.grid_for(pr, prec)
+    if tile_rows:
+        g.set_option(hjw.OPT_TILE_ROWS, tile_rows)
     info = None
     for _ in range(warmup):
         g.set_phi(phi_dev)
@@ -146,7 +149,8 @@ def main():
     for name, prec in [("fp32", hjw.FP32_MIXED), ("fp64", hjw.FP64)]:
         if name == "fp64" and args.skip_fp64:
             continue
-        wall, info, times = time_solves(hjw, pr, prec, phi_dev, args.steps, args.warmup)
+        wall, info, times = time_solves(hjw, pr, prec, phi_dev, args.steps, args.warmup,
+                                        args.tile_rows)
         stages = 3 * info.steps
         results[name] = {"wall": wall, "rk_steps": info.steps, "stages": stages,
                          "cell_updates_per_s": cells * stages * args.steps / wall,

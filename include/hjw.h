@@ -64,9 +64,11 @@ typedef enum { HJW_H_LINEAR = 0, HJW_H_BURGERS = 1, HJW_H_NEGCOS = 2, HJW_H_NORM
 typedef enum {
     HJW_OPT_USE_GRAPH = 0,     /* 1 (default): replay captured HIP graphs of whole RK steps;
                                   0: launch every kernel eagerly.  Results are identical. */
-    HJW_OPT_KERNEL_EVENTS = 1  /* 1: launch eagerly and bracket every kernel of a step with
+    HJW_OPT_KERNEL_EVENTS = 1, /* 1: launch eagerly and bracket every kernel of a step with
                                   HIP events on the grid's stream; resets the totals that
                                   hjw_kernel_times reports.  0 (default): off. */
+    HJW_OPT_TILE_ROWS = 2      /* 2-D tile height: 16 (default: 64 x 16 nodes, 256 threads)
+                                  or 32 (64 x 32 nodes, 512 threads).  Results are identical. */
 } hjw_option;
 
 typedef struct hjw_grid hjw_grid;

@@ -30,9 +30,10 @@ using namespace hjw;
 
 namespace {
 
-// Tile shapes: 64 x 32 nodes per workgroup in 2-D (segments of 8 per thread),
-// 1024 nodes in 1-D (segments of 4).
-constexpr int kTX = 64, kTY = 32, kSX = 8, kSY = 8;
+// Tile shapes: 64 x TY nodes per workgroup in 2-D (segments of 8 per thread;
+// TY = 32 with 512 threads or TY = 16 with 256 threads), 1024 nodes in 1-D
+// (segments of 4).
+constexpr int kTX = 64, kSX = 8, kSY = 8;
 constexpr int kTX1 = 1024, kS1 = 4;
 constexpr int kGraphSteps = 16;
 constexpr int kMaxBatch = 512;  // steps enqueued between two reads of the step state
@@ -113,12 +114,13 @@ __device__ inline void write_partials(const StageArgs<T, P>& a, T lu, T hu, T lv
     }
 }
 
-// Reduce all workgroups' partials and plan the step (256 threads of one workgroup).
+// Reduce all workgroups' partials and plan the step (one workgroup of kFinThreads).
+constexpr int kFinThreads = 1024;
 __device__ void plan_from_partials(const double* partials, int nb, DevState* st, int kind,
                                    const double* p, int dim, double ihx, double ihy) {
-    __shared__ double red[4][5];
+    __shared__ double red[kFinThreads / 64][5];
     double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY, bad = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) {
+    for (int b = threadIdx.x; b < nb; b += kFinThreads) {
         const double* q = partials + size_t(b) * kPartialStride;
         lu = fmin(lu, q[0]);
         hu = fmax(hu, q[1]);
@@ -143,7 +145,7 @@ __device__ void plan_from_partials(const double* partials, int nb, DevState* st,
     if (threadIdx.x == 0) {
         double r[4] = {red[0][0], red[0][1], red[0][2], red[0][3]};
         double b = red[0][4];
-        for (int k = 1; k < 4; ++k) {
+        for (int k = 1; k < kFinThreads / 64; ++k) {
             r[0] = fmin(r[0], red[k][0]);
             r[1] = fmax(r[1], red[k][1]);
             r[2] = fmin(r[2], red[k][2]);
@@ -162,11 +164,15 @@ __device__ void plan_from_partials(const double* partials, int nb, DevState* st,
     }
 }
 
-template <typename T, typename P, int STAGE>
-__global__ __launch_bounds__(512) void k_stage2d(StageArgs<T, P> a) {
-    using TL = Tile<T, P, kTX, kTY, kSX, kSY>;
+// 2 (TX / SX) TY threads: row threads and column threads (16 TY for 64-wide tiles).
+template <typename T, typename P, int STAGE, int TY>
+__global__ __launch_bounds__(16 * TY) void k_stage2d(StageArgs<T, P> a) {
+    using TL = Tile<T, P, kTX, TY, kSX, kSY>;
+    static_assert(TL::kThreads == 16 * TY, "launch bounds");
+    constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
+    __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
     double dt = 0.0, ax = 0.0, ay = 0.0;
     if (STAGE == kStagePre) {
         if (!step_open(a.st)) return;
@@ -179,23 +185,24 @@ __global__ __launch_bounds__(512) void k_stage2d(StageArgs<T, P> a) {
     const int nb = a.nbx * a.nby;
     const int tile = tile_of_block(blockIdx.x, nb, a.remap);
     const int64_t x0 = int64_t(tile % a.nbx) * kTX;
-    const int64_t y0 = int64_t(tile / a.nbx) * kTY;
+    const int64_t y0 = int64_t(tile / a.nbx) * TY;
     const int tid = threadIdx.x;
 
-    TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL);
+    TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
     __syncthreads();
     T vm[kSY], vp[kSY];
-    const bool rows = tid < TL::kHalf;   // wave-uniform: waves 0-3 rows, 4-7 columns
+    const bool rows = tid < TL::kHalf;   // wave-uniform: the first half of the waves march rows
     if (rows)
         TL::sweep_x(tid, a, phiL, uL);
     else
         TL::sweep_y(tid - TL::kHalf, a, phiL, vm, vp);
     __syncthreads();
     Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
-    if (!rows) TL::finish(tid - TL::kHalf, uL, vm, vp, fin);
+    if (!rows) TL::finish(tid - TL::kHalf, uL, vm, vp, phiL, kCenter ? pnL : nullptr, fin);
 
     if (STAGE == kStagePre) {
-        write_partials<8>(a, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad, blockIdx.x);
+        write_partials<TL::kThreads / 64>(a, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad,
+                                          blockIdx.x);
     } else if (STAGE == kStageLast) {
         if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st->bad = 1;
     }
@@ -204,8 +211,10 @@ __global__ __launch_bounds__(512) void k_stage2d(StageArgs<T, P> a) {
 template <typename T, typename P, int STAGE>
 __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     using TL = Tile1D<T, P, kTX1, kS1>;
+    constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
+    __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
     double dt = 0.0, ax = 0.0;
     if (STAGE == kStagePre) {
         if (!step_open(a.st)) return;
@@ -216,12 +225,13 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     }
     const int64_t x0 = int64_t(blockIdx.x) * kTX1;
     const int tid = threadIdx.x;
-    TL::template load<STAGE>(tid, a, x0, dt, ax, 0.0, phiL);
+    TL::template load<STAGE>(tid, a, x0, dt, ax, 0.0, phiL, pnL);
     __syncthreads();
     TL::sweep_x(tid, a, phiL, uL);
     __syncthreads();
     Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
-    for (int c = tid; c < kTX1; c += 256) fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0));
+    for (int c = tid; c < kTX1; c += 256)
+        fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], kCenter ? pnL[c] : P(0));
     if (STAGE == kStagePre) {
         write_partials<4>(a, fin.lo_u, fin.hi_u, T(0), T(0), fin.bad, blockIdx.x);
     } else if (STAGE == kStageLast) {
@@ -230,7 +240,7 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
 }
 
 // One workgroup: the ranges of phi^n's derivatives -> dissipation -> time step.
-__global__ __launch_bounds__(256) void k_finalize(const double* partials, int nb, DevState* st,
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials, int nb, DevState* st,
                                                   int kind, double p0, double p1, double p2,
                                                   double p3, int dim, double ihx, double ihy) {
     __shared__ int s_open;
@@ -319,6 +329,7 @@ struct hjw_grid {
     double* partials = nullptr;
     DevState* state = nullptr;
     int nbx = 0, nby = 0;
+    int tile_rows = 16;  // 2-D tile height (16 or 32)
 
     // host mirror
     DevState* pinned = nullptr;  // pinned host copy of the device state
@@ -351,7 +362,7 @@ void layout(const hjw_grid* g, size_t* off_phi2, size_t* off_flux, size_t* off_p
     const size_t n = size_t(g->cells());
     if (g->dim == 2) {
         *nbx = int((g->nx + kTX - 1) / kTX);
-        *nby = int((g->ny + kTY - 1) / kTY);
+        *nby = int((g->ny + 15) / 16);   // the partials area holds the finest tiling
     } else {
         *nbx = int((g->nx + kTX1 - 1) / kTX1);
         *nby = 1;
@@ -374,12 +385,9 @@ void layout(const hjw_grid* g, size_t* off_phi2, size_t* off_flux, size_t* off_p
 template <typename T, typename P>
 StageArgs<T, P> make_args(const hjw_grid* g) {
     StageArgs<T, P> a{};
-    const size_t n = size_t(g->cells());
     a.phi_n = static_cast<const P*>(g->phi);
     a.phi_s = static_cast<const P*>(g->phi2);
-    a.hbar = static_cast<T*>(g->flux);
-    a.dxa = a.hbar + n;
-    a.dya = a.hbar + 2 * n;
+    a.flux = static_cast<T*>(g->flux);
     a.partials = g->partials;
     a.st = g->state;
     a.nx = g->nx;
@@ -390,8 +398,8 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     a.ihy = P(1.0 / g->dy);
     a.ihxT = T(1.0 / g->dx);
     a.ihyT = T(1.0 / g->dy);
-    a.epsx = T(kEps / (g->dx * g->dx));
-    a.epsy = T(kEps / (g->dy * g->dy));
+    a.epsx = T(4.0 * kEps / (g->dx * g->dx));
+    a.epsy = T(4.0 * kEps / (g->dy * g->dy));
     a.ham = g->ham;
     for (int k = 0; k < 4; ++k) {
         a.hpT[k] = T(g->hp[k]);
@@ -409,8 +417,10 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
 template <typename T, typename P, int STAGE>
 hipError_t launch_stage(const hjw_grid* g, StageArgs<T, P> a) {
     const dim3 grid(unsigned(g->nbx * g->nby));
-    if (g->dim == 2)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE>), grid, dim3(512), 0, g->stream, a);
+    if (g->dim == 2 && g->tile_rows == 32)
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32>), grid, dim3(512), 0, g->stream, a);
+    else if (g->dim == 2)
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16>), grid, dim3(256), 0, g->stream, a);
     else
         hipLaunchKernelGGL((k_stage1d<T, P, STAGE>), grid, dim3(256), 0, g->stream, a);
     return hipGetLastError();
@@ -437,7 +447,7 @@ hipError_t enqueue_step_typed(hjw_grid* g) {
     hipError_t e = timed(g, 0, [&] { return launch_stage<T, P, kStagePre>(g, a); });
     if (e != hipSuccess) return e;
     e = timed(g, 1, [&] {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, g->stream, g->partials,
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, g->stream, g->partials,
                            g->nbx * g->nby, g->state, g->ham, g->hp[0], g->hp[1], g->hp[2],
                            g->hp[3], g->dim, a.ihxD, a.ihyD);
         return hipGetLastError();
@@ -584,7 +594,7 @@ hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const do
     g->bcx = bc[0];
     g->bcy = dim == 2 ? bc[1] : HJW_BC_PERIODIC;
     g->prec = prec;
-    if (dim == 2 && int64_t(g->nx + kTX - 1) / kTX * ((g->ny + kTY - 1) / kTY) > INT32_MAX) {
+    if (dim == 2 && int64_t(g->nx + kTX - 1) / kTX * ((g->ny + 15) / 16) > INT32_MAX) {
         delete g;
         return fail(HJW_EINVAL, "too many tiles");
     }
@@ -628,7 +638,7 @@ hjw_status hjw_bind(hjw_grid* g, void* ws, size_t bytes, void* stream) {
     g->partials = reinterpret_cast<double*>(g->ws + o_part);
     g->state = reinterpret_cast<DevState*>(g->ws + o_state);
     g->nbx = nbx;
-    g->nby = nby;
+    g->nby = g->dim == 2 ? int((g->ny + g->tile_rows - 1) / g->tile_rows) : nby;
     g->bound = true;
     g->phi_set = false;
     g->failed = false;
@@ -776,6 +786,13 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
     if (option == HJW_OPT_USE_GRAPH) {
         g->use_graph = value != 0;
         if (!g->use_graph) drop_graph(g);
+        return HJW_OK;
+    }
+    if (option == HJW_OPT_TILE_ROWS) {
+        if (value != 16 && value != 32) return fail(HJW_EINVAL, "tile rows must be 16 or 32");
+        g->tile_rows = int(value);
+        if (g->dim == 2) g->nby = int((g->ny + g->tile_rows - 1) / g->tile_rows);
+        drop_graph(g);
         return HJW_OK;
     }
     if (option == HJW_OPT_KERNEL_EVENTS) {

@@ -21,7 +21,8 @@ using namespace hjw;
 
 namespace {
 
-constexpr int kTX = 64, kTY = 32, kSX = 8, kSY = 8;
+constexpr int kTX = 64, kSX = 8, kSY = 8;
+int g_tile_rows = 32;  // 2-D tile height being emulated (32 or 16)
 constexpr int kTX1 = 1024, kS1 = 4;
 constexpr size_t kGuard = 4096;
 
@@ -64,10 +65,10 @@ struct Emu {
         : pr(p), n(size_t(p.nx * p.ny)), phi(n), phi2(n), flux(3 * n),
           partials(size_t(tiles(p)) * kPartialStride), d0(n), d1(n), d2(n), d3(n) {
         nbx = p.dim == 2 ? int((p.nx + kTX - 1) / kTX) : int((p.nx + kTX1 - 1) / kTX1);
-        nby = p.dim == 2 ? int((p.ny + kTY - 1) / kTY) : 1;
+        nby = p.dim == 2 ? int((p.ny + g_tile_rows - 1) / g_tile_rows) : 1;
     }
     static int64_t tiles(const Problem& p) {
-        return p.dim == 2 ? ((p.nx + kTX - 1) / kTX) * ((p.ny + kTY - 1) / kTY)
+        return p.dim == 2 ? ((p.nx + kTX - 1) / kTX) * ((p.ny + 15) / 16)
                           : (p.nx + kTX1 - 1) / kTX1;
     }
 
@@ -75,9 +76,7 @@ struct Emu {
         StageArgs<T, P> a{};
         a.phi_n = phi.data();
         a.phi_s = phi2.data();
-        a.hbar = flux.data();
-        a.dxa = flux.data() + n;
-        a.dya = flux.data() + 2 * n;
+        a.flux = flux.data();
         a.dout0 = d0.data();
         a.dout1 = d1.data();
         a.dout2 = d2.data();
@@ -92,8 +91,8 @@ struct Emu {
         a.ihy = P(1.0 / pr.dy);
         a.ihxT = T(1.0 / pr.dx);
         a.ihyT = T(1.0 / pr.dy);
-        a.epsx = T(kEps / (pr.dx * pr.dx));
-        a.epsy = T(kEps / (pr.dy * pr.dy));
+        a.epsx = T(4.0 * kEps / (pr.dx * pr.dx));
+        a.epsy = T(4.0 * kEps / (pr.dy * pr.dy));
         a.ham = pr.ham;
         for (int k = 0; k < 4; ++k) a.hpT[k] = T(pr.hp[k]);
         a.nbx = nbx;
@@ -106,50 +105,67 @@ struct Emu {
     // Run one stage over all tiles, the way the kernel does.
     template <int STAGE>
     void stage(StageArgs<T, P> a, double dt, double ax, double ay) {
+        if (pr.dim == 2 && g_tile_rows == 16)
+            stage2d<STAGE, 16>(a, dt, ax, ay);
+        else if (pr.dim == 2)
+            stage2d<STAGE, 32>(a, dt, ax, ay);
+        else
+            stage1d<STAGE>(a, dt, ax, ay);
+    }
+
+    template <int STAGE, int TY>
+    void stage2d(StageArgs<T, P> a, double dt, double ax, double ay) {
+        using TL = Tile<T, P, kTX, TY, kSX, kSY>;
         const int nb = nbx * nby;
-        if (pr.dim == 2) {
-            using TL = Tile<T, P, kTX, kTY, kSX, kSY>;
-            std::vector<P> phiL(TL::kPhiElems);
-            std::vector<T> uL(TL::kUElems);
-            for (int b = 0; b < nb; ++b) {
-                const int64_t x0 = int64_t(b % nbx) * kTX, y0 = int64_t(b / nbx) * kTY;
-                std::fill(phiL.begin(), phiL.end(), P(NAN));
-                std::fill(uL.begin(), uL.end(), T(NAN));
-                for (int t = 0; t < TL::kThreads; ++t)
-                    TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data());
-                // the row threads and the column threads, then the barrier, then the finish
-                std::vector<T> vm(size_t(TL::kHalf) * kSY), vp(size_t(TL::kHalf) * kSY);
-                for (int t = 0; t < TL::kHalf; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
-                for (int t = 0; t < TL::kHalf; ++t)
-                    TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY]);
-                double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY;
-                bool bad = false;
-                for (int t = 0; t < TL::kHalf; ++t) {
-                    Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
-                    TL::finish(t, uL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY], fin);
-                    lu = std::fmin(lu, double(fin.lo_u));
-                    hu = std::fmax(hu, double(fin.hi_u));
-                    lv = std::fmin(lv, double(fin.lo_v));
-                    hv = std::fmax(hv, double(fin.hi_v));
-                    bad = bad || fin.bad;
-                }
-                write_partial(b, lu, hu, lv, hv, bad);
+        std::vector<P> phiL(TL::kPhiElems), pnL(TL::kCenterElems);
+        std::vector<T> uL(TL::kUElems);
+        constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
+        for (int b = 0; b < nb; ++b) {
+            const int64_t x0 = int64_t(b % nbx) * kTX, y0 = int64_t(b / nbx) * TY;
+            std::fill(phiL.begin(), phiL.end(), P(NAN));
+            std::fill(pnL.begin(), pnL.end(), P(NAN));
+            std::fill(uL.begin(), uL.end(), T(NAN));
+            for (int t = 0; t < TL::kThreads; ++t)
+                TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data(), pnL.data());
+            // the row threads and the column threads, then the barrier, then the finish
+            std::vector<T> vm(size_t(TL::kHalf) * kSY), vp(size_t(TL::kHalf) * kSY);
+            for (int t = 0; t < TL::kHalf; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
+            for (int t = 0; t < TL::kHalf; ++t)
+                TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY]);
+            double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY;
+            bool bad = false;
+            for (int t = 0; t < TL::kHalf; ++t) {
+                Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
+                TL::finish(t, uL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY], phiL.data(),
+                           kCenter ? pnL.data() : nullptr, fin);
+                lu = std::fmin(lu, double(fin.lo_u));
+                hu = std::fmax(hu, double(fin.hi_u));
+                lv = std::fmin(lv, double(fin.lo_v));
+                hv = std::fmax(hv, double(fin.hi_v));
+                bad = bad || fin.bad;
             }
-        } else {
-            using TL = Tile1D<T, P, kTX1, kS1>;
-            std::vector<P> phiL(TL::kPhiElems);
-            std::vector<T> uL(TL::kUElems);
-            for (int b = 0; b < nb; ++b) {
-                const int64_t x0 = int64_t(b) * kTX1;
-                std::fill(phiL.begin(), phiL.end(), P(NAN));
-                std::fill(uL.begin(), uL.end(), T(NAN));
-                for (int t = 0; t < TL::kThreads; ++t)
-                    TL::template load<STAGE>(t, a, x0, dt, ax, 0.0, phiL.data());
-                for (int t = 0; t < TL::kThreads; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
-                Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
-                for (int c = 0; c < kTX1; ++c) fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0));
-                write_partial(b, double(fin.lo_u), double(fin.hi_u), 0.0, 0.0, fin.bad);
-            }
+            write_partial(b, lu, hu, lv, hv, bad);
+        }
+    }
+
+    template <int STAGE>
+    void stage1d(StageArgs<T, P> a, double dt, double ax, double ay) {
+        using TL = Tile1D<T, P, kTX1, kS1>;
+        const int nb = nbx * nby;
+        std::vector<P> phiL(TL::kPhiElems), pnL(TL::kCenterElems);
+        std::vector<T> uL(TL::kUElems);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t x0 = int64_t(b) * kTX1;
+            std::fill(phiL.begin(), phiL.end(), P(NAN));
+            std::fill(pnL.begin(), pnL.end(), P(NAN));
+            std::fill(uL.begin(), uL.end(), T(NAN));
+            for (int t = 0; t < TL::kThreads; ++t)
+                TL::template load<STAGE>(t, a, x0, dt, ax, 0.0, phiL.data(), pnL.data());
+            for (int t = 0; t < TL::kThreads; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
+            Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
+            for (int c = 0; c < kTX1; ++c)
+                fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], pnL[c]);
+            write_partial(b, double(fin.lo_u), double(fin.hi_u), 0.0, 0.0, fin.bad);
         }
     }
 
@@ -246,6 +262,13 @@ int step(const Problem& pr, double* phi, double t, double t_final, double cfl, d
 }  // namespace
 
 extern "C" {
+
+// Height of the emulated 2-D tile (32 or 16), as HJW_OPT_TILE_ROWS selects on the GPU.
+int hjw_emu_set_tile_rows(int rows) {
+    if (rows != 16 && rows != 32) return -1;
+    g_tile_rows = rows;
+    return 0;
+}
 
 // prec: 0 FP64, 1 FP32 stencil with FP64 phi, 2 FP32 phi.  Returns 0, or -7 if
 // a guard zone was written.

@@ -30,6 +30,8 @@
 //   (relative half-gap below TAU) and from the antiderivative otherwise.
 //   With t_k = (eps/h^2 + M_k^2)^2 the weights become products of the other two
 //   t's (one division per side); in FP32 the t's are first scaled by 1/max t.
+//   The weighted sum is formed as the central candidate plus a correction made
+//   of two third differences (see sweep()).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -116,28 +118,28 @@ template <typename T> struct SeriesCfg;
 template <> struct SeriesCfg<double> { static constexpr double tau2 = 4.0e-4; };
 template <> struct SeriesCfg<float> { static constexpr float tau2 = 1.0e-2f; };
 
-// Mean of sqrt(1+s^2) over [m-h, m+h] from the midpoint expansion
-//   M = S (1 + y/6 + y^2 (12 m^2 - 3)/120 + y^3 45 (8 m^4 - 12 m^2 + 1)/5040),
-//   S = sqrt(1+m^2), y = (h/(1+m^2))^2.
-__host__ __device__ inline double mean_series(double m, double h) {
-    const double q = 1.0 + m * m;
-    const double r = rsqrt_t(q);
-    const double S = q * r;
-    const double g = h * r * r;
-    const double y = g * g;
-    const double m2 = m * m;
-    const double c2 = (12.0 * m2 - 3.0) * (1.0 / 120.0);
-    const double c3 = (45.0 / 5040.0) * ((8.0 * m2 - 12.0) * m2 + 1.0);
-    return S + S * y * ((1.0 / 6.0) + y * (c2 + y * c3));
+// Twice the mean of sqrt(1+s^2) between a and b, from the sum sg = a + b and the
+// difference dl = b - a, by the midpoint expansion
+//   2M = sqrt(q4) (1 + g^2 (2/3 + g^2 (2/5 (sg^2-1) + g^2 2/7 (sg^4 - 6 sg^2 + 2)))),
+//   q4 = 4 + sg^2, g = dl / q4
+// (the Taylor series of the mean about m = sg/2 with y = (h/(1+m^2))^2 = 4 g^2).
+__host__ __device__ inline double mean2_series(double sg, double dl, double q4) {
+    const double r = rsqrt_t(q4);
+    const double sq = q4 * r;
+    const double g = dl * r * r;
+    const double g2 = g * g;
+    const double s2 = sg * sg;
+    const double inner =
+        (2.0 / 3.0) + g2 * (0.4 * (s2 - 1.0) + g2 * ((2.0 / 7.0) * (s2 * (s2 - 6.0) + 2.0)));
+    return sq + sq * g2 * inner;
 }
-__host__ __device__ inline float mean_series(float m, float h) {
-    const float q = 1.0f + m * m;
-    const float r = rsqrt_t(q);
-    const float S = q * r;
-    const float g = h * r * r;
-    const float y = g * g;
-    const float c2 = (12.0f * m * m - 3.0f) * (1.0f / 120.0f);
-    return S + S * y * ((1.0f / 6.0f) + y * c2);
+__host__ __device__ inline float mean2_series(float sg, float dl, float q4) {
+    const float r = rsqrt_t(q4);
+    const float sq = q4 * r;
+    const float g = dl * r * r;
+    const float g2 = g * g;
+    const float inner = (2.0f / 3.0f) + g2 * (0.4f * (sg * sg - 1.0f));
+    return sq + sq * g2 * inner;
 }
 
 // Antiderivative of sqrt(1+s^2).
@@ -146,31 +148,37 @@ __host__ __device__ inline T prim(T s) {
     return T(0.5) * (s * sqrt_t(T(1) + s * s) + asinh_t(s));
 }
 
-// Means for the three pairs of one cell: (c0, b1), (c0, c1), (f0, c1).
+// Twice the means for the three pairs of one cell: (c0, b1), (c0, c1), (f0, c1).
+// A pair whose relative half-gap is not small takes the antiderivative instead;
+// the wave takes that branch only when one of its lanes needs it.
 template <typename T>
 __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA, T& MB, T& MC) {
     const T tau2 = SeriesCfg<T>::tau2;
-    const T hA = T(0.5) * (b1 - c0), mA = T(0.5) * (b1 + c0);
-    const T hB = T(0.5) * (c1 - c0), mB = T(0.5) * (c1 + c0);
-    const T hC = T(0.5) * (c1 - f0), mC = T(0.5) * (c1 + f0);
-    const bool wideA = hA * hA >= tau2 * (T(1) + mA * mA);
-    const bool wideB = hB * hB >= tau2 * (T(1) + mB * mB);
-    const bool wideC = hC * hC >= tau2 * (T(1) + mC * mC);
-    MA = mean_series(mA, hA);
-    MB = mean_series(mB, hB);
-    MC = mean_series(mC, hC);
+    const T sA = c0 + b1, dA = b1 - c0;
+    const T sB = c0 + c1, dB = c1 - c0;
+    const T sC = f0 + c1, dC = c1 - f0;
+    const T qA = sA * sA + T(4), qB = sB * sB + T(4), qC = sC * sC + T(4);
+    // half-gap h = dl/2 against tau sqrt(1 + m^2) = tau sqrt(q4)/2
+    const bool wideA = dA * dA >= tau2 * qA;
+    const bool wideB = dB * dB >= tau2 * qB;
+    const bool wideC = dC * dC >= tau2 * qC;
+    MA = mean2_series(sA, dA, qA);
+    MB = mean2_series(sB, dB, qB);
+    MC = mean2_series(sC, dC, qC);
     if (any_lane(wideA || wideB || wideC)) {
         const T Pc0 = prim(c0), Pb1 = prim(b1), Pc1 = prim(c1), Pf0 = prim(f0);
-        if (wideA) MA = (Pb1 - Pc0) / (b1 - c0);
-        if (wideB) MB = (Pc1 - Pc0) / (c1 - c0);
-        if (wideC) MC = (Pc1 - Pf0) / (c1 - f0);
+        if (wideA) MA = T(2) * (Pb1 - Pc0) / dA;
+        if (wideB) MB = T(2) * (Pc1 - Pc0) / dB;
+        if (wideC) MC = T(2) * (Pc1 - Pf0) / dC;
     }
 }
 
-// Products of the weight denominators (see the file comment).
-__host__ __device__ inline void weight_products(double MA, double MB, double MC, double epsp,
+// Products of the weight denominators: with t_k = (eps/h^2 + M_k^2)^2 (up to a
+// common factor), omega_k of eq. (WLOC1) is proportional to d_k times the product
+// of the other two t's.  Inputs are the doubled means and eps4 = 4 eps / h^2.
+__host__ __device__ inline void weight_products(double MA, double MB, double MC, double eps4,
                                                 double& pAB, double& pAC, double& pBC) {
-    double tA = epsp + MA * MA, tB = epsp + MB * MB, tC = epsp + MC * MC;
+    double tA = eps4 + MA * MA, tB = eps4 + MB * MB, tC = eps4 + MC * MC;
     tA *= tA;
     tB *= tB;
     tC *= tC;
@@ -178,9 +186,10 @@ __host__ __device__ inline void weight_products(double MA, double MB, double MC,
     pAC = tA * tC;
     pBC = tB * tC;
 }
-__host__ __device__ inline void weight_products(float MA, float MB, float MC, float epsp,
+// FP32: the t's are first scaled by 1/max t so that no product overflows.
+__host__ __device__ inline void weight_products(float MA, float MB, float MC, float eps4,
                                                 float& pAB, float& pAC, float& pBC) {
-    float tA = epsp + MA * MA, tB = epsp + MB * MB, tC = epsp + MC * MC;
+    float tA = eps4 + MA * MA, tB = eps4 + MB * MB, tC = eps4 + MC * MC;
     const float s = rcp_t(fmaxf(tA, fmaxf(tB, tC)));
     tA *= s;
     tB *= s;
@@ -205,41 +214,54 @@ __host__ __device__ inline float wdiv<float>(float num, float den) {
 // March along one line.  line[k*stride] is phi_s at position p0-3+k,
 // k = 0..S+5; writes phi^-(p0+k) to um[k] and phi^+(p0+k) to up[k], k < S.
 // Differences are formed in the storage precision P and then cast to T.
+//
+// With v_j = Delta^+ phi_j and the cell [x_{i-1}, x_i] seeing (a,b,c,d,e) =
+// v_{i-3..i+1}, first differences e1..e4 of (a..e) give
+//   C_{i-1} = e2/h, C_i = e3/h, B_i = (2 e2 - e1)/h, F_{i-1} = (2 e3 - e4)/h,
+// and the candidates of Step 2 differ from the central one by third differences:
+//   q0 - q1 = D3a/3, q2 - q1 = D3b/6, D3a = a - 3b + 3c - d, D3b = b - 3c + 3d - e,
+//   q1 = c + (e2 + 2 e3)/6 for phi^- at x_i, and mirrored for phi^+ at x_{i-1}:
+//   qp1 = c - (e3 + 2 e2)/6, qp0 - qp1 = -D3b/3, qp2 - qp1 = -D3a/6.
+// So phi^- = q1 + (w0 (q0-q1) + w2 (q2-q1)) / (w0 + w1 + w2), and likewise phi^+.
 template <typename T, typename P, int S>
-__host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T epsp, T* um,
+__host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T eps4, T* um,
                                       T* up) {
     T v[S + 5];
 #pragma unroll
     for (int k = 0; k < S + 5; ++k)
         v[k] = T((line[(k + 1) * stride] - line[k * stride]) * ihP);
-    constexpr T c13 = T(1.0 / 3.0), c76 = T(7.0 / 6.0), c116 = T(11.0 / 6.0);
-    constexpr T c16 = T(1.0 / 6.0), c56 = T(5.0 / 6.0);
+    T e1 = v[1] - v[0], e2 = v[2] - v[1], e3 = v[3] - v[2];
+    T c0 = e2 * ih;
 #pragma unroll
     for (int it = 0; it <= S; ++it) {
-        // the cell [x_{i-1}, x_i], i = p0 + it, sees v_{i-3..i+1}
-        const T a = v[it], b = v[it + 1], c = v[it + 2], d = v[it + 3], e = v[it + 4];
-        const T c0 = (c - b) * ih;                       // C_{i-1}
-        const T c1 = (d - c) * ih;                       // C_i
-        const T b1 = (a - T(3) * b + T(2) * c) * ih;     // B_i
-        const T f0 = (T(3) * d - T(2) * c - e) * ih;     // F_{i-1}
+        const T c = v[it + 2];
+        const T e4 = v[it + 4] - v[it + 3];
+        const T B1 = T(2) * e2 - e1;          // h B_i
+        const T F0 = T(2) * e3 - e4;          // h F_{i-1}
+        const T c1 = e3 * ih;                 // C_i
+        const T b1 = B1 * ih;                 // B_i
+        const T f0 = F0 * ih;                 // F_{i-1}
         T MA, MB, MC;
         cell_means(c0, b1, c1, f0, MA, MB, MC);
         T pAB, pAC, pBC;
-        weight_products(MA, MB, MC, epsp, pAB, pAC, pBC);
+        weight_products(MA, MB, MC, eps4, pAB, pAC, pBC);
+        const T D3a = B1 - e3;                // a - 3b + 3c - d
+        const T D3b = F0 - e2;                // b - 3c + 3d - e
+        const T p6AC = T(6) * pAC;
         if (it < S) {  // phi^- at node i: weights (1/10, 6/10, 3/10) on (A, B, C)
-            const T q0 = c13 * a - c76 * b + c116 * c;
-            const T q1 = -c16 * b + c56 * c + c13 * d;
-            const T q2 = c13 * c + c56 * d - c16 * e;
-            const T w0 = T(0.1) * pBC, w1 = T(0.6) * pAC, w2 = T(0.3) * pAB;
-            um[it] = wdiv(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
+            const T q1 = c + (e2 + T(2) * e3) * T(1.0 / 6.0);
+            const T num = pBC * (D3a * T(1.0 / 3.0)) + pAB * (D3b * T(0.5));
+            um[it] = q1 + wdiv(num, pBC + p6AC + T(3) * pAB);
         }
         if (it > 0) {  // phi^+ at node i-1: the mirrored sub-stencils, (1/10, 6/10, 3/10) on (C, B, A)
-            const T q0 = c13 * e - c76 * d + c116 * c;
-            const T q1 = -c16 * d + c56 * c + c13 * b;
-            const T q2 = c13 * c + c56 * b - c16 * a;
-            const T w0 = T(0.1) * pAB, w1 = T(0.6) * pAC, w2 = T(0.3) * pBC;
-            up[it - 1] = wdiv(w0 * q0 + w1 * q1 + w2 * q2, w0 + w1 + w2);
+            const T qp1 = c - (e3 + T(2) * e2) * T(1.0 / 6.0);
+            const T num = pAB * (D3b * T(1.0 / 3.0)) + pBC * (D3a * T(0.5));
+            up[it - 1] = qp1 - wdiv(num, pAB + p6AC + T(3) * pBC);
         }
+        e1 = e2;
+        e2 = e3;
+        e3 = e4;
+        c0 = c1;
     }
 }
 
@@ -328,14 +350,18 @@ __host__ __device__ inline void plan_step(DevState& s, int kind, const double* p
 }
 
 // ---------------------------------------------------------------- stage arguments
+template <typename T>
+struct Flux3 {
+    T h, dx, dy;
+};
+
 template <typename T, typename P>
 struct StageArgs {
     const P* phi_n;   // phi^n
     const P* phi_s;   // stage input of the last stage (phi_2)
     P* out;           // stage output (phi_2, or phi^{n+1} over phi^n)
-    T* hbar;          // pre-stage outputs: H(ubar, vbar), (u+ - u-)/2, (v+ - v-)/2
-    T* dxa;
-    T* dya;
+    T* flux;          // pre-stage outputs per node, interleaved:
+                      // [3 i] = H(ubar, vbar), [3 i + 1] = (u+ - u-)/2, [3 i + 2] = (v+ - v-)/2
     double* dout0;    // derivative outputs (kStageDeriv)
     double* dout1;
     double* dout2;
@@ -346,7 +372,7 @@ struct StageArgs {
     int bcx, bcy;
     P ihx, ihy;       // 1/dx, 1/dy in the storage precision
     T ihxT, ihyT;
-    T epsx, epsy;     // eps/dx^2, eps/dy^2
+    T epsx, epsy;     // 4 eps/dx^2, 4 eps/dy^2 (the weights use doubled means)
     int ham;
     T hpT[4];
     double hpD[4];    // the same parameters in FP64 (dissipation, time step)
@@ -361,9 +387,10 @@ template <int STAGE, typename T, typename P>
 __host__ __device__ inline P node_value(const StageArgs<T, P>& a, int64_t idx, double dt,
                                         double ax, double ay) {
     if (STAGE == kStageMid) {
-        // phi_1 = phi^n + dt L(phi^n), L = -(Hbar - ax Dx - ay Dy)
-        const double ry = a.dim == 2 ? mul_rn(ay, double(a.dya[idx])) : 0.0;
-        const double r = double(a.hbar[idx]) - (mul_rn(ax, double(a.dxa[idx])) + ry);
+        // phi_1 = phi^n + dt L(phi^n), L = -(Hbar - (ax Dx + ay Dy))
+        const Flux3<T> f = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
+        const double ry = a.dim == 2 ? mul_rn(ay, double(f.dy)) : 0.0;
+        const double r = double(f.h) - (mul_rn(ax, double(f.dx)) + ry);
         return P(double(a.phi_n[idx]) - dt * r);
     } else if (STAGE == kStageLast) {
         return a.phi_s[idx];
@@ -421,25 +448,54 @@ __host__ __device__ inline P stage_value(const StageArgs<T, P>& a, int64_t i, in
 }
 
 // ---------------------------------------------------------------- the tile
-// 512 threads: threads [0, 256) march the rows (phase X) while threads [256, 512)
-// march the columns (phase Y) at the same time; after a barrier the column threads
-// combine their phi_y^-+ with the phi_x^-+ left in LDS by the row threads.
+// 2 * kHalf threads: threads [0, kHalf) march the rows (phase X) while threads
+// [kHalf, 2 kHalf) march the columns (phase Y) at the same time; after a barrier the
+// column threads combine their phi_y^-+ with the phi_x^-+ left in LDS by the row threads.
 template <typename T, typename P, int TX, int TY, int SX, int SY>
 struct Tile {
-    static constexpr int kThreads = 512;
-    static constexpr int kHalf = 256;
+    static constexpr int kHalf = TY * (TX / SX);
+    static constexpr int kThreads = 2 * kHalf;
     static constexpr int PW = TX + 7;      // pitch of the phi tile (odd: fewer bank conflicts)
     static constexpr int PH = TY + 6;
     static constexpr int UW = TX + 1;      // pitch of the phi_x results
     static constexpr int kPhiElems = PH * PW;
     static constexpr int kUElems = 2 * TY * UW;
-    static_assert(TY * (TX / SX) == kHalf, "phase X covers the tile rows");
-    static_assert(TX * (TY / SY) == kHalf, "phase Y covers the tile columns");
+    static constexpr int kCenterElems = TX * TY;   // phi^n on the tile (second/third stage)
+    static_assert(TX * (TY / SY) == kHalf, "phase Y covers the tile columns with as many threads");
+    static_assert(kHalf % 64 == 0, "row and column threads are whole waves");
 
     // Phase 0: phi_s over rows [y0-3, y0+TY+3) x columns [x0-3, x0+TX+3), plus-shaped.
+    // Tiles whose halo lies inside the grid index it directly (TX and TY are powers of
+    // two, so the index arithmetic is shifts and masks); tiles at an edge resolve each
+    // point through the boundary condition.
+    // The second and third stages also keep phi^n of the tile's own nodes in pnL.
     template <int STAGE>
     __host__ __device__ static void load(int tid, const StageArgs<T, P>& a, int64_t x0,
-                                         int64_t y0, double dt, double ax, double ay, P* phiL) {
+                                         int64_t y0, double dt, double ax, double ay, P* phiL,
+                                         P* pnL) {
+        static_assert((TX & (TX - 1)) == 0 && (TY & (TY - 1)) == 0, "power-of-two tile");
+        constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
+        const bool inside = x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx && y0 + TY + 3 <= a.ny;
+        if (inside) {
+            const int64_t base = (y0 - 3) * a.nx + (x0 - 3);   // global index of phiL[0]
+            for (int e = tid; e < TY * TX; e += kThreads) {   // the tile itself
+                const int r = e / TX + 3, c = e % TX + 3;
+                const int64_t idx = base + r * a.nx + c;
+                phiL[r * PW + c] = node_value<STAGE>(a, idx, dt, ax, ay);
+                if (kCenter) pnL[e] = a.phi_n[idx];
+            }
+            for (int e = tid; e < TY * 6; e += kThreads) {    // x halo: 3 columns each side
+                const int r = e % TY + 3, k = e / TY;
+                const int c = k < 3 ? k : TX + k;
+                phiL[r * PW + c] = node_value<STAGE>(a, base + r * a.nx + c, dt, ax, ay);
+            }
+            for (int e = tid; e < 6 * TX; e += kThreads) {    // y halo: 3 rows each side
+                const int k = e / TX, c = e % TX + 3;
+                const int r = k < 3 ? k : TY + k;
+                phiL[r * PW + c] = node_value<STAGE>(a, base + r * a.nx + c, dt, ax, ay);
+            }
+            return;
+        }
         constexpr int kRowElems = TY * (TX + 6);   // rows of the tile with the x halo
         constexpr int kColElems = 6 * TX;          // the three rows above and below
         for (int e = tid; e < kRowElems + kColElems; e += kThreads) {
@@ -455,9 +511,15 @@ struct Tile {
             }
             phiL[r * PW + c] = stage_value<STAGE>(a, x0 + c - 3, y0 + r - 3, dt, ax, ay);
         }
+        if (kCenter) {
+            for (int e = tid; e < TY * TX; e += kThreads) {
+                const int64_t i = x0 + e % TX, j = y0 + e / TX;
+                if (i < a.nx && j < a.ny) pnL[e] = a.phi_n[j * a.nx + i];
+            }
+        }
     }
 
-    // Phase X, t in [0, 256): (row, segment); phi_x^- / phi_x^+ into uL[0|1][row][x].
+    // Phase X, t in [0, kHalf): (row, segment); phi_x^- / phi_x^+ into uL[0|1][row][x].
     __host__ __device__ static void sweep_x(int t, const StageArgs<T, P>& a, const P* phiL,
                                             T* uL) {
         const int row = t % TY;
@@ -471,7 +533,7 @@ struct Tile {
         }
     }
 
-    // Phase Y, t in [0, 256): (column, segment); phi_y^- / phi_y^+ into registers.
+    // Phase Y, t in [0, kHalf): (column, segment); phi_y^- / phi_y^+ into registers.
     __host__ __device__ static void sweep_y(int t, const StageArgs<T, P>& a, const P* phiL, T* vm,
                                             T* vp) {
         const int col = t % TX;
@@ -479,15 +541,18 @@ struct Tile {
         sweep<T, P, SY>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy, vm, vp);
     }
 
-    // After the barrier: fin(col, row, um, up, vm, vp) for the thread's SY nodes.
+    // After the barrier: fin(col, row, um, up, vm, vp, phi_s, phi^n) for the thread's SY
+    // nodes, with the stage input and phi^n of the node taken from LDS.
     template <class Fin>
-    __host__ __device__ static void finish(int t, const T* uL, const T* vm, const T* vp, Fin& fin) {
+    __host__ __device__ static void finish(int t, const T* uL, const T* vm, const T* vp,
+                                           const P* phiL, const P* pnL, Fin& fin) {
         const int col = t % TX;
         const int seg = t / TX;
 #pragma unroll
         for (int k = 0; k < SY; ++k) {
             const int row = seg * SY + k;
-            fin(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col], vm[k], vp[k]);
+            fin(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col], vm[k], vp[k],
+                phiL[(row + 3) * PW + col + 3], pnL ? pnL[row * TX + col] : P(0));
         }
     }
 };
@@ -501,11 +566,16 @@ struct Tile1D {
     static constexpr int kUElems = 2 * TX;
     static_assert(TX / S == kThreads, "sweep covers the tile");
 
+    static constexpr int kCenterElems = TX;
+
     template <int STAGE>
     __host__ __device__ static void load(int tid, const StageArgs<T, P>& a, int64_t x0,
-                                         double dt, double ax, double ay, P* phiL) {
+                                         double dt, double ax, double ay, P* phiL, P* pnL) {
         for (int c = tid; c < PW; c += kThreads)
             phiL[c] = stage_value<STAGE>(a, x0 + c - 3, 0, dt, ax, ay);
+        if (STAGE == kStageMid || STAGE == kStageLast)
+            for (int c = tid; c < TX; c += kThreads)
+                if (x0 + c < a.nx) pnL[c] = a.phi_n[x0 + c];
     }
 
     __host__ __device__ static void sweep_x(int tid, const StageArgs<T, P>& a, const P* phiL,
@@ -537,7 +607,9 @@ struct Finisher {
         : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), lo_u(T(INFINITY)),
           hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {}
 
-    __host__ __device__ void operator()(int col, int row, T um, T up, T vm, T vp) {
+    // ps: the stage input at the node (phi_1 in the second stage, phi_2 in the third);
+    // pn: phi^n at the node (second and third stages).
+    __host__ __device__ void operator()(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
         const int64_t i = x0 + col, j = y0 + row;
         if (i >= a.nx || j >= a.ny) return;
         const int64_t idx = j * a.nx + i;
@@ -554,9 +626,7 @@ struct Finisher {
         const T Dx = T(0.5) * (up - um), Dy = T(0.5) * (vp - vm);
         const T H = hamiltonian(a.ham, a.hpT, ub, vb);
         if (STAGE == kStagePre) {
-            a.hbar[idx] = H;
-            a.dxa[idx] = Dx;
-            if (dim == 2) a.dya[idx] = Dy;
+            reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{H, Dx, Dy};
             lo_u = fmin(lo_u, fmin(um, up));
             hi_u = fmax(hi_u, fmax(um, up));
             lo_v = fmin(lo_v, fmin(vm, vp));
@@ -566,14 +636,12 @@ struct Finisher {
         }
         // L = -(H - (ax Dx + ay Dy)); the sum is symmetric in x and y
         const T R = H - (mul_rn(T(ax), Dx) + mul_rn(T(ay), Dy));
-        const double pn = double(a.phi_n[idx]);
+        const double pn = double(pn_);
         double res;
         if (STAGE == kStageMid) {
-            const double p1 = double(node_value<kStageMid>(a, idx, dt, ax, ay));
-            res = 0.75 * pn + 0.25 * (p1 - dt * double(R));
+            res = 0.75 * pn + 0.25 * (double(ps) - dt * double(R));
         } else {
-            const double p2 = double(a.phi_s[idx]);
-            res = (1.0 / 3.0) * pn + (2.0 / 3.0) * (p2 - dt * double(R));
+            res = (1.0 / 3.0) * pn + (2.0 / 3.0) * (double(ps) - dt * double(R));
         }
         const P outv = P(res);
         a.out[idx] = outv;

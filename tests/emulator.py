@@ -21,11 +21,17 @@ def lib():
         L.hjw_emu_derivatives.restype = ctypes.c_int
         L.hjw_emu_derivatives.argtypes = [ctypes.c_int, i64, i64, d, d, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.hjw_emu_set_tile_rows.restype = ctypes.c_int
+        L.hjw_emu_set_tile_rows.argtypes = [ctypes.c_int]
         L.hjw_emu_step.restype = ctypes.c_int
         L.hjw_emu_step.argtypes = [ctypes.c_int, i64, i64, d, d, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, vp, vp, d, d, d, vp]
         _lib = L
     return _lib
+
+
+def set_tile_rows(rows):
+    assert lib().hjw_emu_set_tile_rows(int(rows)) == 0
 
 
 def _p(a):

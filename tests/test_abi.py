@@ -62,7 +62,7 @@ def test_workspace_is_the_hbm_footprint(prec, per_cell):
     nb = ctypes.c_size_t()
     assert L.hjw_workspace_bytes(h, ctypes.byref(nb)) == 0
     cells = 1024 * 1024
-    tiles = (1024 // 64) * (1024 // 32)
+    tiles = (1024 // 64) * (1024 // 16)   # partials sized for the finest tiling
     assert per_cell * cells <= nb.value <= per_cell * cells + tiles * 40 + 4096
     L.hjw_grid_destroy(h)
 

@@ -14,13 +14,23 @@ from paper_1909_13263_amd import workloads as W
 # derivative (relative to the largest derivative on the grid).
 TOL = {0: 1e-13, 1: 2e-6, 2: 2e-5}
 
-SHAPES = [(8,), (37,), (160,), (1030,), (8, 8), (33, 65), (40, 70), (64, 64), (96, 130)]
+# (100, 200) and (135, 260) hold tiles whose halo is inside the grid (the direct-index
+# load path); the others exercise edge tiles and ragged tails.
+SHAPES = [(8,), (37,), (160,), (1030,), (8, 8), (33, 65), (40, 70), (64, 64), (96, 130),
+          (100, 200), (135, 260)]
+
+
+@pytest.fixture(params=[32, 16], ids=["tile64x32", "tile64x16"])
+def tile_rows(request):
+    EM.set_tile_rows(request.param)
+    yield request.param
+    EM.set_tile_rows(32)
 
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("bc", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_emulated_derivatives_match_oracle(shape, bc, prec):
+def test_emulated_derivatives_match_oracle(shape, bc, prec, tile_rows):
     rng = np.random.default_rng(len(shape) * 1000 + sum(shape))
     phi = W.random_smooth_periodic(shape, seed=sum(shape)) + 0.05 * rng.normal(size=shape)
     h = tuple(0.05 + 0.01 * a for a in range(len(shape)))
@@ -33,12 +43,13 @@ def test_emulated_derivatives_match_oracle(shape, bc, prec):
 
 def _cases():
     return [W.burgers1d(160), W.advect1d(37), W.negcos1d(50), W.burgers2d(96, ny=70),
-            W.negcos2d(65, ny=33), W.levelset2d(100, ny=72)]
+            W.negcos2d(65, ny=33), W.levelset2d(100, ny=72), W.burgers2d(200, ny=100),
+            W.levelset2d(260, ny=135)]
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(8))
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_emulated_rk3_step_matches_oracle(case, prec):
+def test_emulated_rk3_step_matches_oracle(case, prec, tile_rows):
     pr = _cases()[case]
     phi = pr.phi0()
     prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc)

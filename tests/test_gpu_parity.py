@@ -43,7 +43,7 @@ def _field(shape, seed):
 
 # --------------------------------------------------------------------------- derivatives
 DERIV_SHAPES = [(8,), (37,), (160,), (1030,), (2500,), (8, 8), (33, 65), (40, 70), (96, 130),
-                (256, 256)]
+                (100, 200), (135, 260), (256, 256)]
 DERIV_TOL = {FP64: 1e-13, MIXED: 2e-6, FP32: 2e-5}
 
 
@@ -82,6 +82,7 @@ STEP_CASES = [
     lambda: W.burgers1d(160), lambda: W.advect1d(37), lambda: W.negcos1d(50),
     lambda: W.burgers2d(96, ny=70), lambda: W.negcos2d(65, ny=33),
     lambda: W.levelset2d(100, ny=72), lambda: W.burgers2d(256),
+    lambda: W.levelset2d(260, ny=135),
 ]
 STEP_TOL = {FP64: 1e-14, MIXED: 1e-7, FP32: 1e-6}
 
