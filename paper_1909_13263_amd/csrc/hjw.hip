@@ -1,12 +1,13 @@
 // hjw.hip - HIP kernels for gfx950 and the C ABI declared in include/hjw.h.
 //
-// One TVD-RK3 step (Rathan & Biswas, arXiv:1909.13263, Step 5) is four launches:
+// One TVD-RK3 step (Rathan & Biswas, arXiv:1909.13263, Step 5) is three launches:
 //   k_stage<Pre>   WENO-L derivatives of phi^n (Steps 1-4), writes Hbar = H(ubar,vbar),
-//                  Dx = (u+ - u-)/2, Dy = (v+ - v-)/2 and per-block min/max of u+-, v+-;
-//   k_finalize     one workgroup: the ranges -> alpha_x, alpha_y (eq. LF, maximum of
-//                  |H_p| over the box) -> dt (CFL rule) -> step state;
-//   k_stage<Mid>   rebuilds phi_1 = phi^n - dt (Hbar - ax Dx - ay Dy) on the tile and
-//                  its halo, derivatives of phi_1, phi_2 = 3/4 phi^n + 1/4 (phi_1 + dt L);
+//                  Dx = (u+ - u-)/2, Dy = (v+ - v-)/2 and folds the workgroup's min/max
+//                  of u+-, v+- into range slots;
+//   k_stage<Mid>   every workgroup reduces the slots -> alpha_x, alpha_y (eq. LF, maximum
+//                  of |H_p| over the box) -> dt (CFL rule); rebuilds
+//                  phi_1 = phi^n - dt (Hbar - ax Dx - ay Dy) on the tile and its halo,
+//                  derivatives of phi_1, phi_2 = 3/4 phi^n + 1/4 (phi_1 + dt L);
 //   k_stage<Last>  derivatives of phi_2, phi^{n+1} = 1/3 phi^n + 2/3 (phi_2 + dt L),
 //                  written in place over phi^n.
 // The step state lives on the device, so whole steps are captured once in a HIP
@@ -70,8 +71,8 @@ __device__ inline T wave_max(T x) {
     return x;
 }
 
-__device__ inline bool step_open(const DevState* st) {
-    return st->bad == 0 && st->t < st->t_final && st->steps_left > 0;
+__device__ inline bool step_open(const DevState& s) {
+    return s.bad == 0 && s.t < s.t_final && s.steps_left > 0;
 }
 
 __device__ inline int tile_of_block(int bid, int nb, int remap) {
@@ -80,9 +81,28 @@ __device__ inline int tile_of_block(int bid, int nb, int remap) {
     return remap ? (bid % 8) * (nb / 8) + bid / 8 : bid;
 }
 
+// Range accumulators: the first stage of a step folds each workgroup's min/max of
+// the one-sided derivatives into one of kSlots slots with integer atomics on an
+// order-preserving key of the FP64 value (exact, independent of order); the second
+// stage reduces the slots in every workgroup and derives the same time step.
+constexpr int kSlots = 64;
+struct RangeSlots {
+    unsigned long long key[4][kSlots];   // min u, max u, min v, max v
+    unsigned int bad[kSlots];
+};
+
+// Monotone map from doubles to unsigned 64-bit keys and back.
+__device__ inline unsigned long long order_key(double x) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline double key_value(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double(static_cast<long long>(b));
+}
+
 template <int NW, typename T, typename P>
-__device__ inline void write_partials(const StageArgs<T, P>& a, T lu, T hu, T lv, T hv, bool bad,
-                                      int bid) {
+__device__ inline void fold_range(const StageArgs<T, P>& a, T lu, T hu, T lv, T hv, bool bad) {
     __shared__ double red[NW][4];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     lu = wave_min(lu);
@@ -105,63 +125,92 @@ __device__ inline void write_partials(const StageArgs<T, P>& a, T lu, T hu, T lv
             r2 = fmin(r2, red[k][2]);
             r3 = fmax(r3, red[k][3]);
         }
-        double* p = a.partials + size_t(bid) * kPartialStride;
-        p[0] = r0;
-        p[1] = r1;
-        p[2] = r2;
-        p[3] = r3;
-        p[4] = anybad ? 1.0 : 0.0;
+        RangeSlots* sl = static_cast<RangeSlots*>(a.slots);
+        const int k = blockIdx.x % kSlots;
+        atomicMin(&sl->key[0][k], order_key(r0));
+        atomicMax(&sl->key[1][k], order_key(r1));
+        atomicMin(&sl->key[2][k], order_key(r2));
+        atomicMax(&sl->key[3][k], order_key(r3));
+        if (anybad) atomicOr(&sl->bad[k], 1u);
     }
 }
 
-// Reduce all workgroups' partials and plan the step (one workgroup of kFinThreads).
-constexpr int kFinThreads = 1024;
-__device__ void plan_from_partials(const double* partials, int nb, DevState* st, int kind,
-                                   const double* p, int dim, double ihx, double ihy) {
-    __shared__ double red[kFinThreads / 64][5];
-    double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY, bad = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kFinThreads) {
-        const double* q = partials + size_t(b) * kPartialStride;
-        lu = fmin(lu, q[0]);
-        hu = fmax(hu, q[1]);
-        lv = fmin(lv, q[2]);
-        hv = fmax(hv, q[3]);
-        bad = fmax(bad, q[4]);
-    }
-    lu = wave_min(lu);
-    hu = wave_max(hu);
-    lv = wave_min(lv);
-    hv = wave_max(hv);
-    bad = wave_max(bad);
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    if (lane == 0) {
-        red[w][0] = lu;
-        red[w][1] = hu;
-        red[w][2] = lv;
-        red[w][3] = hv;
-        red[w][4] = bad;
+// Second stage: every workgroup reduces the slots and plans the step from the step
+// record st[par] (read-only during this launch); workgroup 0 publishes the result in
+// st[par ^ 1].  Returns whether the step is taken; dt and the dissipation go to the
+// references.
+template <typename T, typename P>
+__device__ inline bool plan_in_block(const StageArgs<T, P>& a, double& dt, double& ax,
+                                     double& ay) {
+    __shared__ DevState s_plan;
+    if (threadIdx.x < 64) {
+        const RangeSlots* sl = static_cast<const RangeSlots*>(a.slots);
+        const int k = threadIdx.x;
+        double r0 = key_value(sl->key[0][k]), r1 = key_value(sl->key[1][k]);
+        double r2 = key_value(sl->key[2][k]), r3 = key_value(sl->key[3][k]);
+        unsigned int b = sl->bad[k];
+        r0 = wave_min(r0);
+        r1 = wave_max(r1);
+        r2 = wave_min(r2);
+        r3 = wave_max(r3);
+        b = __any(b != 0u) ? 1u : 0u;
+        if (threadIdx.x == 0) {
+            DevState s = a.st[a.par];
+            if (step_open(s)) {
+                const double r[4] = {r0, r1, r2, r3};
+                if (b != 0u || !(finite_t(r0) && finite_t(r1) && finite_t(r2) && finite_t(r3))) {
+                    s.bad = 1;
+                    s.active = 0;
+                } else {
+                    plan_step(s, a.ham, a.hpD, a.dim, a.ihxD, a.ihyD, r);
+                    s.active = s.bad ? 0 : 1;
+                }
+            } else {
+                s.active = 0;   // nothing to do: carry the record over unchanged
+            }
+            s_plan = s;
+            if (blockIdx.x == 0) a.st[a.par ^ 1] = s;
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double r[4] = {red[0][0], red[0][1], red[0][2], red[0][3]};
-        double b = red[0][4];
-        for (int k = 1; k < kFinThreads / 64; ++k) {
-            r[0] = fmin(r[0], red[k][0]);
-            r[1] = fmax(r[1], red[k][1]);
-            r[2] = fmin(r[2], red[k][2]);
-            r[3] = fmax(r[3], red[k][3]);
-            b = fmax(b, red[k][4]);
-        }
-        DevState s = *st;
-        s.active = 0;
-        if (b != 0.0 || !(finite_t(r[0]) && finite_t(r[1]) && finite_t(r[2]) && finite_t(r[3]))) {
-            s.bad = 1;
-        } else {
-            plan_step(s, kind, p, dim, ihx, ihy, r);
-            s.active = s.bad ? 0 : 1;
-        }
-        *st = s;
+    dt = s_plan.dt;
+    ax = s_plan.alpha_x;
+    ay = s_plan.alpha_y;
+    return s_plan.active != 0;
+}
+
+// Third stage, workgroup 0: empty the slots for the next step's first stage.
+template <typename T, typename P>
+__device__ inline void clear_slots(const StageArgs<T, P>& a) {
+    if (blockIdx.x == 0 && threadIdx.x < kSlots) {
+        RangeSlots* sl = static_cast<RangeSlots*>(a.slots);
+        const int k = threadIdx.x;
+        sl->key[0][k] = ~0ull;
+        sl->key[1][k] = 0ull;
+        sl->key[2][k] = ~0ull;
+        sl->key[3][k] = 0ull;
+        sl->bad[k] = 0u;
     }
+}
+
+// Entry of a stage kernel: whether this workgroup has work, and the step's dt and
+// dissipation for the second and third stages.
+template <int STAGE, typename T, typename P>
+__device__ inline bool stage_entry(const StageArgs<T, P>& a, double& dt, double& ax,
+                                   double& ay) {
+    dt = ax = ay = 0.0;
+    if (STAGE == kStagePre) return step_open(a.st[a.par]);
+    if (STAGE == kStageMid) return plan_in_block(a, dt, ax, ay);
+    if (STAGE == kStageLast) {
+        const DevState& n = a.st[a.par ^ 1];
+        if (!n.active) return false;
+        dt = n.dt;
+        ax = n.alpha_x;
+        ay = n.alpha_y;
+        clear_slots(a);
+        return true;
+    }
+    return true;
 }
 
 // 2 (TX / SX) TY threads: row threads and column threads (16 TY for 64-wide tiles).
@@ -173,22 +222,22 @@ __global__ __launch_bounds__(16 * TY) void k_stage2d(StageArgs<T, P> a) {
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
     __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
-    double dt = 0.0, ax = 0.0, ay = 0.0;
-    if (STAGE == kStagePre) {
-        if (!step_open(a.st)) return;
-    } else if (STAGE == kStageMid || STAGE == kStageLast) {
-        if (!a.st->active) return;
-        dt = a.st->dt;
-        ax = a.st->alpha_x;
-        ay = a.st->alpha_y;
-    }
     const int nb = a.nbx * a.nby;
     const int tile = tile_of_block(blockIdx.x, nb, a.remap);
     const int64_t x0 = int64_t(tile % a.nbx) * kTX;
     const int64_t y0 = int64_t(tile / a.nbx) * TY;
     const int tid = threadIdx.x;
-
-    TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
+    double dt, ax, ay;
+    if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
+        // issue the tile's loads before the step plan so that their latencies overlap
+        typename TL::Gathered gth;
+        TL::gather(tid, a, x0, y0, phiL, pnL, gth);
+        if (!stage_entry<STAGE>(a, dt, ax, ay)) return;   // uniform over the workgroup
+        TL::make_phi1(tid, a, dt, ax, ay, phiL, gth);
+    } else {
+        if (!stage_entry<STAGE>(a, dt, ax, ay)) return;
+        TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
+    }
     __syncthreads();
     T vm[kSY], vp[kSY];
     const bool rows = tid < TL::kHalf;   // wave-uniform: the first half of the waves march rows
@@ -201,10 +250,9 @@ __global__ __launch_bounds__(16 * TY) void k_stage2d(StageArgs<T, P> a) {
     if (!rows) TL::finish(tid - TL::kHalf, uL, vm, vp, phiL, kCenter ? pnL : nullptr, fin);
 
     if (STAGE == kStagePre) {
-        write_partials<TL::kThreads / 64>(a, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad,
-                                          blockIdx.x);
+        fold_range<TL::kThreads / 64>(a, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad);
     } else if (STAGE == kStageLast) {
-        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st->bad = 1;
+        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
     }
 }
 
@@ -215,14 +263,8 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
     __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
-    double dt = 0.0, ax = 0.0;
-    if (STAGE == kStagePre) {
-        if (!step_open(a.st)) return;
-    } else if (STAGE == kStageMid || STAGE == kStageLast) {
-        if (!a.st->active) return;
-        dt = a.st->dt;
-        ax = a.st->alpha_x;
-    }
+    double dt, ax, ay;
+    if (!stage_entry<STAGE>(a, dt, ax, ay)) return;
     const int64_t x0 = int64_t(blockIdx.x) * kTX1;
     const int tid = threadIdx.x;
     TL::template load<STAGE>(tid, a, x0, dt, ax, 0.0, phiL, pnL);
@@ -233,25 +275,10 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     for (int c = tid; c < kTX1; c += 256)
         fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], kCenter ? pnL[c] : P(0));
     if (STAGE == kStagePre) {
-        write_partials<4>(a, fin.lo_u, fin.hi_u, T(0), T(0), fin.bad, blockIdx.x);
+        fold_range<4>(a, fin.lo_u, fin.hi_u, T(0), T(0), fin.bad);
     } else if (STAGE == kStageLast) {
-        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st->bad = 1;
+        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
     }
-}
-
-// One workgroup: the ranges of phi^n's derivatives -> dissipation -> time step.
-__global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials, int nb, DevState* st,
-                                                  int kind, double p0, double p1, double p2,
-                                                  double p3, int dim, double ihx, double ihy) {
-    __shared__ int s_open;
-    if (threadIdx.x == 0) s_open = step_open(st) ? 1 : 0;
-    __syncthreads();
-    if (!s_open) {
-        if (threadIdx.x == 0) st->active = 0;
-        return;
-    }
-    const double p[4] = {p0, p1, p2, p3};
-    plan_from_partials(partials, nb, st, kind, p, dim, ihx, ihy);
 }
 
 __global__ void k_set_target(DevState* st, double t_final, double cfl, int64_t steps_left) {
@@ -263,8 +290,9 @@ __global__ void k_set_target(DevState* st, double t_final, double cfl, int64_t s
     }
 }
 
-__global__ void k_reset(DevState* st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+// Both step records to t = 0 and empty range slots.
+__global__ void k_reset(DevState* st, RangeSlots* sl) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) {
         DevState s;
         s.t = 0.0;
         s.t_final = 0.0;
@@ -278,7 +306,15 @@ __global__ void k_reset(DevState* st) {
         s.active = 0;
         s.bad = 0;
         s.pad[0] = s.pad[1] = 0;
-        *st = s;
+        st[threadIdx.x] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kSlots) {
+        const int k = threadIdx.x;
+        sl->key[0][k] = ~0ull;
+        sl->key[1][k] = 0ull;
+        sl->key[2][k] = ~0ull;
+        sl->key[3][k] = 0ull;
+        sl->bad[k] = 0u;
     }
 }
 
@@ -326,8 +362,9 @@ struct hjw_grid {
     void* phi = nullptr;
     void* phi2 = nullptr;
     void* flux = nullptr;  // Hbar, Dx, Dy back to back
-    double* partials = nullptr;
-    DevState* state = nullptr;
+    DevState* state = nullptr;   // two step records, st[par] is the current one
+    void* slots = nullptr;       // range accumulators
+    int par = 0;
     int nbx = 0, nby = 0;
     int tile_rows = 16;  // 2-D tile height (16 or 32)
 
@@ -339,8 +376,7 @@ struct hjw_grid {
 
     // graphs
     bool use_graph = true;
-    bool graph_ok = false;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};   // by the parity the replay starts at
 
     // per-kernel event timing (eager launches only)
     bool timing = false;
@@ -362,7 +398,7 @@ void layout(const hjw_grid* g, size_t* off_phi2, size_t* off_flux, size_t* off_p
     const size_t n = size_t(g->cells());
     if (g->dim == 2) {
         *nbx = int((g->nx + kTX - 1) / kTX);
-        *nby = int((g->ny + 15) / 16);   // the partials area holds the finest tiling
+        *nby = int((g->ny + 15) / 16);
     } else {
         *nbx = int((g->nx + kTX1 - 1) / kTX1);
         *nby = 1;
@@ -375,10 +411,11 @@ void layout(const hjw_grid* g, size_t* off_phi2, size_t* off_flux, size_t* off_p
     *off_flux = o;
     // three flux arrays, and at least 8n bytes (an FP64 staging area in FP32 mode)
     o += align256(std::max(size_t(3) * n * g->elem_flux(), n * 8));
-    *off_part = o;
-    o += align256(nb * kPartialStride * sizeof(double));
-    *off_state = o;
-    o += align256(sizeof(DevState));
+    (void)nb;
+    *off_part = o;                       // range slots
+    o += align256(sizeof(RangeSlots));
+    *off_state = o;                      // two step records
+    o += align256(2 * sizeof(DevState));
     *total = o;
 }
 
@@ -388,8 +425,9 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     a.phi_n = static_cast<const P*>(g->phi);
     a.phi_s = static_cast<const P*>(g->phi2);
     a.flux = static_cast<T*>(g->flux);
-    a.partials = g->partials;
     a.st = g->state;
+    a.par = g->par;
+    a.slots = g->slots;
     a.nx = g->nx;
     a.ny = g->ny;
     a.bcx = g->bcx;
@@ -444,14 +482,8 @@ hipError_t timed(hjw_grid* g, int kind, Fn fn) {
 template <typename T, typename P>
 hipError_t enqueue_step_typed(hjw_grid* g) {
     StageArgs<T, P> a = make_args<T, P>(g);
+    g->par ^= 1;   // every enqueued step moves the current record to the other slot
     hipError_t e = timed(g, 0, [&] { return launch_stage<T, P, kStagePre>(g, a); });
-    if (e != hipSuccess) return e;
-    e = timed(g, 1, [&] {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, g->stream, g->partials,
-                           g->nbx * g->nby, g->state, g->ham, g->hp[0], g->hp[1], g->hp[2],
-                           g->hp[3], g->dim, a.ihxD, a.ihyD);
-        return hipGetLastError();
-    });
     if (e != hipSuccess) return e;
     a.out = static_cast<P*>(g->phi2);
     e = timed(g, 2, [&] { return launch_stage<T, P, kStageMid>(g, a); });
@@ -483,41 +515,45 @@ hipError_t enqueue_deriv_typed(const hjw_grid* g, double* um, double* up, double
 }
 
 void drop_graph(hjw_grid* g) {
-    if (g->graph) (void)hipGraphExecDestroy(g->graph);
-    g->graph = nullptr;
-    g->graph_ok = false;
+    for (auto& gr : g->graph) {
+        if (gr) (void)hipGraphExecDestroy(gr);
+        gr = nullptr;
+    }
 }
 
+// Capture kGraphSteps whole steps starting at the current parity.  kGraphSteps is
+// even, so a replay leaves the parity where it found it.
 hjw_status build_graph(hjw_grid* g) {
-    drop_graph(g);
+    static_assert(kGraphSteps % 2 == 0, "replays must preserve the record parity");
+    const int par0 = g->par;
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     for (int s = 0; s < kGraphSteps && e == hipSuccess; ++s) e = enqueue_step(g);
     hipError_t e2 = hipStreamEndCapture(g->stream, &graph);
+    g->par = par0;
     if (e != hipSuccess || e2 != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
         return fail(HJW_EHIP, "graph capture failed: %s / %s", hipGetErrorString(e),
                     hipGetErrorString(e2));
     }
-    hipError_t e3 = hipGraphInstantiate(&g->graph, graph, nullptr, nullptr, 0);
+    hipError_t e3 = hipGraphInstantiate(&g->graph[par0], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) {
-        g->graph = nullptr;
+        g->graph[par0] = nullptr;
         return fail(HJW_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
     }
-    g->graph_ok = true;
     return HJW_OK;
 }
 
 hjw_status enqueue_steps(hjw_grid* g, int64_t n) {
     if (g->use_graph && !g->timing && n >= kGraphSteps) {
-        if (!g->graph_ok) {
+        if (!g->graph[g->par]) {
             hjw_status s = build_graph(g);
             if (s != HJW_OK) return s;
         }
         while (n >= kGraphSteps) {
-            HIP_TRY(hipGraphLaunch(g->graph, g->stream));
+            HIP_TRY(hipGraphLaunch(g->graph[g->par], g->stream));
             n -= kGraphSteps;
         }
     }
@@ -526,8 +562,8 @@ hjw_status enqueue_steps(hjw_grid* g, int64_t n) {
 }
 
 hjw_status read_state(hjw_grid* g) {
-    HIP_TRY(hipMemcpyAsync(g->pinned, g->state, sizeof(DevState), hipMemcpyDeviceToHost,
-                           g->stream));
+    HIP_TRY(hipMemcpyAsync(g->pinned, g->state + g->par, sizeof(DevState),
+                           hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->last = *g->pinned;
     for (int k = 0; k < g->ev_used; ++k) {
@@ -635,14 +671,16 @@ hjw_status hjw_bind(hjw_grid* g, void* ws, size_t bytes, void* stream) {
     g->phi = g->ws;
     g->phi2 = g->ws + o_phi2;
     g->flux = g->ws + o_flux;
-    g->partials = reinterpret_cast<double*>(g->ws + o_part);
+    g->slots = g->ws + o_part;
     g->state = reinterpret_cast<DevState*>(g->ws + o_state);
+    g->par = 0;
     g->nbx = nbx;
     g->nby = g->dim == 2 ? int((g->ny + g->tile_rows - 1) / g->tile_rows) : nby;
     g->bound = true;
     g->phi_set = false;
     g->failed = false;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g->stream, g->state);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g->stream, g->state,
+                       static_cast<RangeSlots*>(g->slots));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->last = DevState{};
@@ -676,7 +714,9 @@ hjw_status hjw_set_phi(hjw_grid* g, const double* phi0, int on_device) {
     // FP64 input lands in phi itself, or in the flux area when phi is FP32
     double* src = g->prec == HJW_FP32 ? static_cast<double*>(g->flux) : static_cast<double*>(g->phi);
     HIP_TRY(hipMemcpyAsync(src, phi0, n * sizeof(double), kind, g->stream));
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g->stream, g->state);
+    g->par = 0;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g->stream, g->state,
+                       static_cast<RangeSlots*>(g->slots));
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, g->stream, src, int64_t(n),
                        g->state);
@@ -706,7 +746,7 @@ hjw_status hjw_step_to(hjw_grid* g, double t_final, double cfl, int64_t max_step
     if (!std::isfinite(t_final) || !(cfl > 0.0) || !std::isfinite(cfl))
         return fail(HJW_EINVAL, "need finite t_final and cfl > 0");
     const int64_t limit = max_steps > 0 ? max_steps : std::numeric_limits<int64_t>::max();
-    hipLaunchKernelGGL(k_set_target, dim3(1), dim3(64), 0, g->stream, g->state, t_final, cfl,
+    hipLaunchKernelGGL(k_set_target, dim3(1), dim3(64), 0, g->stream, g->state + g->par, t_final, cfl,
                        limit);
     HIP_TRY(hipGetLastError());
     s = read_state(g);

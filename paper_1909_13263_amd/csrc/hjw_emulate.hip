@@ -81,8 +81,9 @@ struct Emu {
         a.dout1 = d1.data();
         a.dout2 = d2.data();
         a.dout3 = d3.data();
-        a.partials = partials.data();
         a.st = &st;
+        a.par = 0;
+        a.slots = nullptr;
         a.nx = pr.nx;
         a.ny = pr.ny;
         a.bcx = pr.bcx;
@@ -125,8 +126,17 @@ struct Emu {
             std::fill(phiL.begin(), phiL.end(), P(NAN));
             std::fill(pnL.begin(), pnL.end(), P(NAN));
             std::fill(uL.begin(), uL.end(), T(NAN));
-            for (int t = 0; t < TL::kThreads; ++t)
-                TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data(), pnL.data());
+            if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
+                // the kernel's split second stage: gather, plan, then phi_1 in place
+                std::vector<typename TL::Gathered> gth(TL::kThreads);
+                for (int t = 0; t < TL::kThreads; ++t)
+                    TL::gather(t, a, x0, y0, phiL.data(), pnL.data(), gth[t]);
+                for (int t = 0; t < TL::kThreads; ++t)
+                    TL::make_phi1(t, a, dt, ax, ay, phiL.data(), gth[t]);
+            } else {
+                for (int t = 0; t < TL::kThreads; ++t)
+                    TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data(), pnL.data());
+            }
             // the row threads and the column threads, then the barrier, then the finish
             std::vector<T> vm(size_t(TL::kHalf) * kSY), vp(size_t(TL::kHalf) * kSY);
             for (int t = 0; t < TL::kHalf; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());

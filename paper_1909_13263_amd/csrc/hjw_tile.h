@@ -72,7 +72,7 @@ struct DevState {
     int32_t pad[2];
 };
 
-// Block partials written by the pre-stage: min/max of u+-, v+- and a bad flag.
+// Block partials of the CPU emulation: min/max of u+-, v+- and a bad flag.
 constexpr int kPartialStride = 5;
 
 // ---------------------------------------------------------------- math helpers
@@ -366,8 +366,9 @@ struct StageArgs {
     double* dout1;
     double* dout2;
     double* dout3;
-    double* partials;
-    DevState* st;
+    DevState* st;     // two step records; this step reads st[par] and writes st[par ^ 1]
+    int par;
+    void* slots;      // range accumulators of the first stage (see the kernels)
     int64_t nx, ny;
     int bcx, bcy;
     P ihx, ihy;       // 1/dx, 1/dy in the storage precision
@@ -475,24 +476,14 @@ struct Tile {
                                          P* pnL) {
         static_assert((TX & (TX - 1)) == 0 && (TY & (TY - 1)) == 0, "power-of-two tile");
         constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
-        const bool inside = x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx && y0 + TY + 3 <= a.ny;
-        if (inside) {
+        if (inside(a, x0, y0)) {
             const int64_t base = (y0 - 3) * a.nx + (x0 - 3);   // global index of phiL[0]
-            for (int e = tid; e < TY * TX; e += kThreads) {   // the tile itself
-                const int r = e / TX + 3, c = e % TX + 3;
+            for (int e = tid; e < kPlusElems; e += kThreads) {
+                int r, c;
+                plus_node(e, r, c);
                 const int64_t idx = base + r * a.nx + c;
                 phiL[r * PW + c] = node_value<STAGE>(a, idx, dt, ax, ay);
-                if (kCenter) pnL[e] = a.phi_n[idx];
-            }
-            for (int e = tid; e < TY * 6; e += kThreads) {    // x halo: 3 columns each side
-                const int r = e % TY + 3, k = e / TY;
-                const int c = k < 3 ? k : TX + k;
-                phiL[r * PW + c] = node_value<STAGE>(a, base + r * a.nx + c, dt, ax, ay);
-            }
-            for (int e = tid; e < 6 * TX; e += kThreads) {    // y halo: 3 rows each side
-                const int k = e / TX, c = e % TX + 3;
-                const int r = k < 3 ? k : TY + k;
-                phiL[r * PW + c] = node_value<STAGE>(a, base + r * a.nx + c, dt, ax, ay);
+                if (kCenter && e < TY * TX) pnL[e] = a.phi_n[idx];
             }
             return;
         }
@@ -515,6 +506,69 @@ struct Tile {
             for (int e = tid; e < TY * TX; e += kThreads) {
                 const int64_t i = x0 + e % TX, j = y0 + e / TX;
                 if (i < a.nx && j < a.ny) pnL[e] = a.phi_n[j * a.nx + i];
+            }
+        }
+    }
+
+    // Second stage on a tile whose halo lies inside the grid, split around the step
+    // plan: gather() stages phi^n of the plus-shaped region in phiL (and of the tile in
+    // pnL) and keeps the region's flux records in registers; after dt and the
+    // dissipation are known, make_phi1() turns phiL into phi_1 in place, with the same
+    // arithmetic as node_value().  Element e maps to the same node in both calls.
+    static constexpr int kPlusElems = TY * TX + TY * 6 + 6 * TX;
+    static constexpr int kPerThread = (kPlusElems + kThreads - 1) / kThreads;
+    struct Gathered {
+        Flux3<T> f[kPerThread];
+    };
+    __host__ __device__ static void plus_node(int e, int& r, int& c) {
+        if (e < TY * TX) {
+            r = e / TX + 3;
+            c = e % TX + 3;
+        } else if (e < TY * TX + TY * 6) {
+            const int f = e - TY * TX;
+            r = f % TY + 3;
+            const int k = f / TY;
+            c = k < 3 ? k : TX + k;
+        } else {
+            const int f = e - TY * TX - TY * 6;
+            const int k = f / TX;
+            c = f % TX + 3;
+            r = k < 3 ? k : TY + k;
+        }
+    }
+    __host__ __device__ static bool inside(const StageArgs<T, P>& a, int64_t x0, int64_t y0) {
+        return x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx && y0 + TY + 3 <= a.ny;
+    }
+    __host__ __device__ static void gather(int tid, const StageArgs<T, P>& a, int64_t x0,
+                                           int64_t y0, P* phiL, P* pnL, Gathered& g) {
+        const int64_t base = (y0 - 3) * a.nx + (x0 - 3);
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int e = tid + j * kThreads;
+            if (e < kPlusElems) {
+                int r, c;
+                plus_node(e, r, c);
+                const int64_t idx = base + r * a.nx + c;
+                const P pn = a.phi_n[idx];
+                phiL[r * PW + c] = pn;
+                g.f[j] = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
+                if (e < TY * TX) pnL[e] = pn;
+            }
+        }
+    }
+    __host__ __device__ static void make_phi1(int tid, const StageArgs<T, P>& a, double dt,
+                                              double ax, double ay, P* phiL,
+                                              const Gathered& g) {
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int e = tid + j * kThreads;
+            if (e < kPlusElems) {
+                int r, c;
+                plus_node(e, r, c);
+                const Flux3<T> f = g.f[j];
+                const double ry = a.dim == 2 ? mul_rn(ay, double(f.dy)) : 0.0;
+                const double rr = double(f.h) - (mul_rn(ax, double(f.dx)) + ry);
+                phiL[r * PW + c] = P(double(phiL[r * PW + c]) - dt * rr);
             }
         }
     }
