@@ -35,20 +35,31 @@ ALGO_SLOTS_PER_CELL = 200 + 28 * 4
 METRIC = "cell-updates/s per RK3 stage (FP32 vs FP64, %HBM peak); served p50/p99 latency"
 
 # Compulsory HBM bytes per node of each kernel of a step (read stage inputs once, write
-# outputs once): [pre, finalize, mid, last] for (phi bytes, flux bytes).
+# outputs once) for (phi bytes, flux bytes).
 def kernel_bytes_per_cell(phi_b, flux_b):
     return {
         "pre": phi_b + 3 * flux_b,                 # read phi^n; write Hbar, Dx, Dy
-        "finalize": 0.0,
         "mid": phi_b + 3 * flux_b + phi_b,         # read phi^n, Hbar, Dx, Dy; write phi_2
         "last": 2 * phi_b + phi_b,                 # read phi^n, phi_2; write phi^{n+1}
     }
 
 
-# HBM bytes per launch of the FP32-stencil kernels at 1024 x 1024 from rocprofv3 counters
-# (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors a 256 MiB copy kernel reads for its known
-# bytes); None when the kernel changed after the counters were taken.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch of the FP32-stencil kernels on the benchmark grid, from rocprofv3
+# counters: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
+# counters read for a plain 256 MiB copy kernel.  Valid only for the kernel sources whose
+# SHA-256 is recorded; any change to them turns the figure into null until re-measured.
+MEASURED_TRAFFIC = {"source_sha256": "5b2bf539aba67f33fbf0218a5dae1bde9a4ff0fb8795a5632e361ba70497064b",
+                    "n": 1024, "tile_rows": 16,
+                    "bytes": {"pre": 22138394, "mid": 31241380, "last": 26292146}}
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hjw_tile.h", "hjw.hip"):
+        with open(os.path.join(ROOT, "paper_1909_13263_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def parse():
@@ -95,12 +106,10 @@ def time_solves(hjw, pr, prec, phi_dev, steps, warmup, tile_rows=0):
         info = g.step_to(pr.t_final, pr.cfl)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # instrumented solve: every kernel bracketed by HIP events on the library's stream
-    g.set_option(hjw.OPT_KERNEL_EVENTS, 1)
+    # kernel durations: each stage kernel launched back to back between HIP events on
+    # the library's stream, on this grid and data, right after the timed region
     g.set_phi(phi_dev)
-    g.step_to(pr.t_final, pr.cfl)
-    times = g.kernel_times()
-    g.set_option(hjw.OPT_KERNEL_EVENTS, 0)
+    times = g.time_kernels(reps=50)
     g.close()
     return wall, info, times
 
@@ -159,12 +168,15 @@ def main():
     main_res = results["fp32"]
     # dominant kernel of the FP32-stencil path
     ktimes = main_res["kernels"]
-    dom = max(("pre", "mid", "last"), key=lambda k: ktimes[k][0])
-    dom_ms = ktimes[dom][0] / max(1, ktimes[dom][1])
+    dom = max(("pre", "mid", "last"), key=lambda k: ktimes[k])
+    dom_ms = ktimes[dom]
     bpc = kernel_bytes_per_cell(8, 4)[dom]
     hbm_gbs = bpc * cells / (dom_ms * 1e-3) / 1e9
     alu_achieved = ALGO_SLOTS_PER_CELL * cells / (dom_ms * 1e-3) / 1e9
-    traffic = MEASURED_TRAFFIC.get((args.n, dom))
+    traffic = None
+    if (MEASURED_TRAFFIC["source_sha256"] == kernel_source_sha()
+            and args.n == MEASURED_TRAFFIC["n"] and args.tile_rows in (0, MEASURED_TRAFFIC["tile_rows"])):
+        traffic = MEASURED_TRAFFIC["bytes"].get(dom)
     # whole-step compulsory bytes per cell-stage: (8 + 8+8 + 8+8 ... ) averaged over stages
     step_bytes = sum(kernel_bytes_per_cell(8, 4).values())
     sustained = step_bytes * cells * main_res["rk_steps"] * args.steps / main_res["wall"] / 1e9
@@ -195,13 +207,13 @@ def main():
         "hbm": {"kernel_GBps": hbm_gbs, "kernel_frac": hbm_gbs / HBM_PEAK_GBS,
                 "sustained_GBps": sustained, "sustained_frac": sustained / HBM_PEAK_GBS,
                 "peak_GBps": HBM_PEAK_GBS},
-        "kernel_ms": {k: (v[0] / max(1, v[1])) for k, v in ktimes.items()},
+        "kernel_ms": ktimes,
     }
     if "fp64" in results:
         r = results["fp64"]
         line["fp64"] = {"value": r["cell_updates_per_s"], "ms_per_step": r["ms_per_solve"],
                         "rk_steps": r["rk_steps"],
-                        "kernel_ms": {k: (v[0] / max(1, v[1])) for k, v in r["kernels"].items()}}
+                        "kernel_ms": r["kernels"]}
         line["fp32_speedup_over_fp64"] = main_res["cell_updates_per_s"] / r["cell_updates_per_s"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)

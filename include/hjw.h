@@ -129,6 +129,13 @@ hjw_status hjw_set_option(hjw_grid *g, int option, int64_t value);
  * [2] second stage, [3] third stage.  ms[4] and count[4] are caller-owned. */
 hjw_status hjw_kernel_times(const hjw_grid *g, double *ms, int64_t *count);
 
+/* Average duration in milliseconds of each of the three stage kernels of a step
+ * (ms[0] first, ms[1] second, ms[2] third stage), each launched reps times back to
+ * back on the grid's stream between two HIP events, on the grid's current phi.
+ * Takes one real step first; afterwards phi is undefined and must be set again
+ * (hjw_set_phi) before stepping. */
+hjw_status hjw_time_kernels(hjw_grid *g, int reps, double *ms);
+
 /* Release the grid (its graphs, events and own stream); the workspace is the
  * caller's.  NULL is ignored. */
 void hjw_grid_destroy(hjw_grid *g);

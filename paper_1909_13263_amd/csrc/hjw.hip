@@ -503,6 +503,19 @@ hipError_t enqueue_step(hjw_grid* g) {
     }
 }
 
+// Stage kernel k (0 first, 1 second, 2 third) against the records of the current parity.
+template <typename T, typename P>
+hipError_t launch_kind(const hjw_grid* g, int k) {
+    StageArgs<T, P> a = make_args<T, P>(g);
+    if (k == 0) return launch_stage<T, P, kStagePre>(g, a);
+    if (k == 1) {
+        a.out = static_cast<P*>(g->phi2);
+        return launch_stage<T, P, kStageMid>(g, a);
+    }
+    a.out = static_cast<P*>(g->phi);
+    return launch_stage<T, P, kStageLast>(g, a);
+}
+
 template <typename T, typename P>
 hipError_t enqueue_deriv_typed(const hjw_grid* g, double* um, double* up, double* vm,
                                double* vp) {
@@ -850,6 +863,55 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
         return HJW_OK;
     }
     return fail(HJW_EINVAL, "unknown option %d", option);
+}
+
+hjw_status hjw_time_kernels(hjw_grid* g, int reps, double* ms) {
+    hjw_status s = check_ready(g);
+    if (s != HJW_OK) return s;
+    if (!g->phi_set || !g->ham_set) return fail(HJW_ESTATE, "phi or Hamiltonian not set");
+    if (reps < 1 || !ms) return fail(HJW_EINVAL, "need reps >= 1 and an output array");
+    // one real step towards a far target, so that every stage kernel finds an open
+    // step (first stage) or a planned one (second and third stages)
+    const int64_t limit = std::numeric_limits<int64_t>::max();
+    hipLaunchKernelGGL(k_set_target, dim3(1), dim3(64), 0, g->stream, g->state + g->par,
+                       std::numeric_limits<double>::max(), 0.5, limit);
+    HIP_TRY(hipGetLastError());
+    const bool timing = g->timing;
+    g->timing = false;
+    HIP_TRY(enqueue_step(g));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t err = hipSuccess;
+    g->par ^= 1;   // launch against the records of the step just taken
+    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+        err = hipEventRecord(e0, g->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) {
+            switch (g->prec) {
+            case HJW_FP64:
+                err = launch_kind<double, double>(g, k);
+                break;
+            case HJW_FP32_MIXED:
+                err = launch_kind<float, double>(g, k);
+                break;
+            default:
+                err = launch_kind<float, float>(g, k);
+            }
+        }
+        if (err == hipSuccess) err = hipEventRecord(e1, g->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        ms[k] = double(t) / reps;
+    }
+    g->par ^= 1;
+    g->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g->phi_set = false;   // phi was overwritten by the repeated third stage
+    if (err != hipSuccess) return fail(HJW_EHIP, "kernel timing failed: %s", hipGetErrorString(err));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return HJW_OK;
 }
 
 hjw_status hjw_kernel_times(const hjw_grid* g, double* ms, int64_t* count) {

@@ -75,6 +75,7 @@ def lib():
             "hjw_get_info": (ctypes.c_int, [vp, ctypes.POINTER(_Info)]),
             "hjw_set_option": (ctypes.c_int, [vp, ctypes.c_int, i64]),
             "hjw_kernel_times": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
+            "hjw_time_kernels": (ctypes.c_int, [vp, ctypes.c_int, dp]),
             "hjw_grid_destroy": (None, [vp]),
             "hjw_last_error": (ctypes.c_char_p, []),
             "hjw_version": (ctypes.c_char_p, []),
@@ -189,6 +190,13 @@ class Grid:
         cnt = (ctypes.c_int64 * 4)()
         _check(lib().hjw_kernel_times(self._h, ms, cnt))
         return {KERNEL_NAMES[k]: (ms[k], int(cnt[k])) for k in range(4)}
+
+    def time_kernels(self, reps=50):
+        """Average ms per launch of the three stage kernels, reps back-to-back launches each
+        between HIP events.  Leaves phi undefined (set it again before stepping)."""
+        ms = (ctypes.c_double * 3)()
+        _check(lib().hjw_time_kernels(self._h, int(reps), ms))
+        return {"pre": ms[0], "mid": ms[1], "last": ms[2]}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -275,3 +275,17 @@ def test_workspace_too_small_is_rejected():
     with pytest.raises(hjw.HJWError) as e:
         hjw.Grid((256, 256), (0, 0), (1, 1), 0, FP64, workspace=ws)
     assert e.value.code == hjw.ENOMEM
+
+
+def test_time_kernels_contract():
+    """hjw_time_kernels returns positive per-launch durations and leaves phi unset."""
+    pr = W.burgers2d(256)
+    g = hjw.grid_for(pr, MIXED)
+    g.set_phi(pr.phi0())
+    ms = g.time_kernels(reps=3)
+    assert all(v > 0 for v in ms.values()), ms
+    with pytest.raises(hjw.HJWError) as e:
+        g.step_to(0.01, 0.5)
+    assert e.value.code == hjw.ESTATE
+    g.set_phi(pr.phi0())
+    g.step_to(0.001, 0.5)
