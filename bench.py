@@ -56,7 +56,7 @@ MEASURED_TRAFFIC = {"source_sha256": "5b2bf539aba67f33fbf0218a5dae1bde9a4ff0fb87
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("hjw_tile.h", "hjw.hip"):
+    for f in ("hjw_tile.h", "hjw_kernels.h", "hjw_common.h", "hjw.hip"):
         with open(os.path.join(ROOT, "paper_1909_13263_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -72,6 +72,14 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0, help="16 or 32 (0: library default)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
+    ap.add_argument("--serve-requests", type=int, default=2048)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the measured saturation rate")
+    ap.add_argument("--serve-pool-gib", type=float, default=4.0)
+    ap.add_argument("--serve-max-active", type=int, default=256)
+    ap.add_argument("--serve-sat-sample", type=int, default=256,
+                    help="requests submitted at once to measure the saturation rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -134,6 +142,46 @@ def cpu_baseline(pr, seconds):
             "kind": "oracle",
             "sample": f"{steps} RK3 steps of the {pr.shape[1]}x{pr.shape[0]} grid from t=0 "
                       f"({wall:.1f} s, FP64 C, OpenMP over grid lines)"}
+
+
+def served_stream(args, hjw):
+    """The served stream: Poisson arrivals of mixed solves at a fraction of the measured
+    saturation rate, continuous batching on one pool; p50/p99 latency and throughput."""
+    from paper_1909_13263_amd import serve as S
+    from paper_1909_13263_amd import workloads as W
+    reqs = W.served_stream(count=args.serve_requests, rate=1.0)
+    t0 = time.perf_counter()
+    phi0s = S.prepare(reqs)
+    prep = time.perf_counter() - t0
+    pool = int(args.serve_pool_gib * (1 << 30))
+    srv = hjw.Server(hjw.FP32_MIXED, pool_bytes=pool, max_active=args.serve_max_active)
+    # warm the graphs and the code paths, then measure the saturation rate: a sample of
+    # the stream submitted at once and drained
+    S.saturation(srv, reqs[:16], phi0s[:16])
+    k = min(args.serve_sat_sample, len(reqs))
+    sat_rps, sat_cells, sat_wall = S.saturation(srv, reqs[-k:], phi0s[-k:])
+    rate = args.serve_load * sat_rps
+    before = srv.stats()
+    t1 = time.perf_counter()
+    recs = S.run_stream(srv, reqs, phi0s, time_scale=1.0 / rate)
+    wall = time.perf_counter() - t1
+    after = srv.stats()
+    summary = S.summarize(recs, wall)
+    srv.close()
+    return {
+        "requests": summary["requests"], "failed": summary["failed"],
+        "precision": "f32 stencil, f64 phi/dt/accumulation",
+        "arrival_rate_rps": rate, "load": args.serve_load,
+        "saturation_rps": sat_rps, "saturation_cell_updates_per_s": sat_cells,
+        "saturation_sample": f"last {k} requests of the stream submitted at once ({sat_wall:.1f} s)",
+        "p50_ms": summary["p50_ms"], "p90_ms": summary["p90_ms"], "p99_ms": summary["p99_ms"],
+        "max_ms": summary["max_ms"], "mean_ms": summary["mean_ms"],
+        "cell_updates_per_s": summary["cell_updates"] / wall,
+        "wall_s": wall, "batched_steps": after["batched_steps"] - before["batched_steps"],
+        "pool_gib": args.serve_pool_gib, "pool_peak_gib": after["pool_peak"] / (1 << 30),
+        "max_active": args.serve_max_active, "phi0_prep_s": prep,
+        "latency_from": "scheduled arrival to result in host memory",
+    }
 
 
 def main():
@@ -215,6 +263,8 @@ def main():
                         "rk_steps": r["rk_steps"],
                         "kernel_ms": r["kernels"]}
         line["fp32_speedup_over_fp64"] = main_res["cell_updates_per_s"] / r["cell_updates_per_s"]
+    if not args.no_serve:
+        line["served"] = served_stream(args, hjw)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(line))

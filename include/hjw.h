@@ -140,6 +140,78 @@ hjw_status hjw_time_kernels(hjw_grid *g, int reps, double *ms);
  * caller's.  NULL is ignored. */
 void hjw_grid_destroy(hjw_grid *g);
 
+/* ----------------------------------------------------------------------------
+ * Served stream: many independent 2-D solves batched into the same launches.
+ *
+ * A server owns no memory: the caller gives it a device pool, from which it
+ * places each admitted solve's phi, stage buffer and flux records (the footprint
+ * hjw_server_footprint reports).  Requests are admitted first-in first-out as
+ * soon as a slot and pool space are free; every batched step advances each
+ * admitted solve by one RK3 step with its own dt, in three launches that cover
+ * the tiles of all admitted solves; solves that reach t_final are retired, their
+ * phi copied to host memory and their pool space released, and waiting requests
+ * are admitted in their place (continuous batching).  Each solve's result is the
+ * same as that of hjw_step_to on the same grid with the same precision.
+ * One server is not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct hjw_server hjw_server;
+
+typedef struct {
+    int64_t n[2];      /* nodes along x and y (>= 8 each)                        */
+    double lo[2];      /* domain, as for hjw_grid_create                          */
+    double hi[2];
+    int bc[2];         /* hjw_bc per axis                                         */
+    int ham;           /* hjw_ham                                                 */
+    double params[4];  /* Hamiltonian parameters                                  */
+    double t_final;    /* solve from t = 0 to t_final                             */
+    double cfl;        /* CFL number, as for hjw_step_to                          */
+} hjw_request;
+
+typedef struct {
+    int64_t submitted, queued, active, done, failed;
+    int64_t batched_steps;   /* batched steps launched                         */
+    double node_stages;      /* nodes x RK stages advanced, all solves        */
+    size_t pool_bytes, pool_in_use, pool_peak;
+} hjw_server_stats;
+
+/* Pool bytes one request occupies while admitted (prec as in hjw_prec). */
+hjw_status hjw_server_footprint(int prec, const hjw_request *req, size_t *bytes);
+
+/* Create a server over a caller-owned device pool (256-byte aligned) for up to
+ * max_active concurrent solves (1..1024); hip_stream as for hjw_bind. */
+hjw_status hjw_server_create(int prec, void *dev_pool, size_t pool_bytes, int max_active,
+                             void *hip_stream, hjw_server **out);
+
+/* Queue a request with phi0 (FP64 host array of n[0]*n[1] values, copied).
+ * HJW_ENOMEM if the request could never fit the pool.  *id receives its id. */
+hjw_status hjw_server_submit(hjw_server *s, const hjw_request *req, const double *phi0,
+                             int64_t *id);
+
+/* Admit, run up to `chunks` chunks of batched steps (each chunk ends with
+ * retirement and admission), and return; returns at once when nothing is queued
+ * or admitted.  *active and *queued (optional) receive the counts on return. */
+hjw_status hjw_server_run(hjw_server *s, int chunks, int64_t *active, int64_t *queued);
+
+/* Ids of requests finished (done or failed) since the last call, up to cap. */
+hjw_status hjw_server_completed(hjw_server *s, int64_t *ids, int cap, int *count);
+
+/* Result of a finished request: phi (FP64 host array, may be NULL), its step
+ * info, and its submit and finish times in seconds on the server's clock.
+ * Returns the request's own status (HJW_OK, or HJW_ENONFINITE if it failed) and
+ * releases it; HJW_ESTATE if the request is not finished. */
+hjw_status hjw_server_result(hjw_server *s, int64_t id, double *phi_out, hjw_info *info,
+                             double *t_submit, double *t_finish);
+
+/* Counters of the server since creation. */
+hjw_status hjw_server_get_stats(const hjw_server *s, hjw_server_stats *stats);
+
+/* Seconds on the server's clock (the clock of t_submit / t_finish). */
+double hjw_server_clock(const hjw_server *s);
+
+/* Release the server (its graphs and own stream); queued and admitted requests are
+ * dropped.  The pool is the caller's.  NULL is ignored. */
+void hjw_server_destroy(hjw_server *s);
+
 /* Thread-local description of the last error ("" if none). */
 const char *hjw_last_error(void);
 

@@ -13,9 +13,11 @@ EMU = os.path.join(PKG, "libhjw_emu.so")
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", INCLUDE, "-I", CSRC]
+# Translation units of the library: the single-grid API and the batched server.
+LIB_SOURCES = ("hjw.hip", "hjw_server.hip")
 
 
 def _hipcc():
@@ -29,15 +31,27 @@ def _run(cmd):
 
 
 def build_library(out: str = LIB) -> str:
+    """Compile the library's translation units in parallel, then link them."""
+    objs, procs = [], []
+    for src in LIB_SOURCES:
+        obj = out + "." + os.path.splitext(src)[0] + ".o"
+        objs.append(obj)
+        procs.append((subprocess.Popen([_hipcc(), f"--offload-arch={ARCH}", *COMMON, "-c",
+                                        os.path.join(CSRC, src), "-o", obj]), src))
+    failed = [src for p, src in procs if p.wait() != 0]
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
     tmp = out + ".tmp"
-    _run([_hipcc(), f"--offload-arch={ARCH}", *COMMON, os.path.join(CSRC, "hjw.hip"), "-o", tmp])
+    _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", *objs, "-o", tmp])
     os.replace(tmp, out)
+    for obj in objs:
+        os.remove(obj)
     return out
 
 
 def build_emulator(out: str = EMU) -> str:
     tmp = out + ".tmp"
-    _run([_hipcc(), f"--offload-arch={ARCH}", "--offload-host-only", *COMMON,
+    _run([_hipcc(), f"--offload-arch={ARCH}", "--offload-host-only", "-shared", *COMMON,
           os.path.join(CSRC, "hjw_emulate.hip"), "-o", tmp])
     os.replace(tmp, out)
     return out

@@ -1,4 +1,4 @@
-// hjw.hip - HIP kernels for gfx950 and the C ABI declared in include/hjw.h.
+// hjw.hip - the single-grid C ABI declared in include/hjw.h (kernels in hjw_kernels.h).
 //
 // One TVD-RK3 step (Rathan & Biswas, arXiv:1909.13263, Step 5) is three launches:
 //   k_stage<Pre>   WENO-L derivatives of phi^n (Steps 1-4), writes Hbar = H(ubar,vbar),
@@ -25,320 +25,22 @@
 #include <vector>
 
 #include "hjw.h"
-#include "hjw_tile.h"
+#include "hjw_common.h"
+#include "hjw_kernels.h"
 
 using namespace hjw;
 
+namespace hjw {
+std::string& last_error() {
+    thread_local std::string text;
+    return text;
+}
+}  // namespace hjw
+
 namespace {
 
-// Tile shapes: 64 x TY nodes per workgroup in 2-D (segments of 8 per thread;
-// TY = 32 with 512 threads or TY = 16 with 256 threads), 1024 nodes in 1-D
-// (segments of 4).
-constexpr int kTX = 64, kSX = 8, kSY = 8;
-constexpr int kTX1 = 1024, kS1 = 4;
 constexpr int kGraphSteps = 16;
 constexpr int kMaxBatch = 512;  // steps enqueued between two reads of the step state
-
-thread_local std::string g_last_error;
-
-hjw_status fail(hjw_status code, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                     \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess)                                                             \
-            return fail(HJW_EHIP, "%s failed: %s (%d)", #expr, hipGetErrorString(e_),     \
-                        int(e_));                                                         \
-    } while (0)
-
-// ------------------------------------------------------------------ kernels
-template <typename T>
-__device__ inline T wave_min(T x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
-    return x;
-}
-template <typename T>
-__device__ inline T wave_max(T x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
-    return x;
-}
-
-__device__ inline bool step_open(const DevState& s) {
-    return s.bad == 0 && s.t < s.t_final && s.steps_left > 0;
-}
-
-__device__ inline int tile_of_block(int bid, int nb, int remap) {
-    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of
-    // tiles so that tile halos are shared through that XCD's L2.
-    return remap ? (bid % 8) * (nb / 8) + bid / 8 : bid;
-}
-
-// Range accumulators: the first stage of a step folds each workgroup's min/max of
-// the one-sided derivatives into one of kSlots slots with integer atomics on an
-// order-preserving key of the FP64 value (exact, independent of order); the second
-// stage reduces the slots in every workgroup and derives the same time step.
-constexpr int kSlots = 64;
-struct RangeSlots {
-    unsigned long long key[4][kSlots];   // min u, max u, min v, max v
-    unsigned int bad[kSlots];
-};
-
-// Monotone map from doubles to unsigned 64-bit keys and back.
-__device__ inline unsigned long long order_key(double x) {
-    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ inline double key_value(unsigned long long k) {
-    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
-    return __longlong_as_double(static_cast<long long>(b));
-}
-
-template <int NW, typename T, typename P>
-__device__ inline void fold_range(const StageArgs<T, P>& a, T lu, T hu, T lv, T hv, bool bad) {
-    __shared__ double red[NW][4];
-    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-    lu = wave_min(lu);
-    hu = wave_max(hu);
-    lv = wave_min(lv);
-    hv = wave_max(hv);
-    const int anybad = __syncthreads_or(bad ? 1 : 0);
-    if (lane == 0) {
-        red[w][0] = double(lu);
-        red[w][1] = double(hu);
-        red[w][2] = double(lv);
-        red[w][3] = double(hv);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r0 = red[0][0], r1 = red[0][1], r2 = red[0][2], r3 = red[0][3];
-        for (int k = 1; k < NW; ++k) {
-            r0 = fmin(r0, red[k][0]);
-            r1 = fmax(r1, red[k][1]);
-            r2 = fmin(r2, red[k][2]);
-            r3 = fmax(r3, red[k][3]);
-        }
-        RangeSlots* sl = static_cast<RangeSlots*>(a.slots);
-        const int k = blockIdx.x % kSlots;
-        atomicMin(&sl->key[0][k], order_key(r0));
-        atomicMax(&sl->key[1][k], order_key(r1));
-        atomicMin(&sl->key[2][k], order_key(r2));
-        atomicMax(&sl->key[3][k], order_key(r3));
-        if (anybad) atomicOr(&sl->bad[k], 1u);
-    }
-}
-
-// Second stage: every workgroup reduces the slots and plans the step from the step
-// record st[par] (read-only during this launch); workgroup 0 publishes the result in
-// st[par ^ 1].  Returns whether the step is taken; dt and the dissipation go to the
-// references.
-template <typename T, typename P>
-__device__ inline bool plan_in_block(const StageArgs<T, P>& a, double& dt, double& ax,
-                                     double& ay) {
-    __shared__ DevState s_plan;
-    if (threadIdx.x < 64) {
-        const RangeSlots* sl = static_cast<const RangeSlots*>(a.slots);
-        const int k = threadIdx.x;
-        double r0 = key_value(sl->key[0][k]), r1 = key_value(sl->key[1][k]);
-        double r2 = key_value(sl->key[2][k]), r3 = key_value(sl->key[3][k]);
-        unsigned int b = sl->bad[k];
-        r0 = wave_min(r0);
-        r1 = wave_max(r1);
-        r2 = wave_min(r2);
-        r3 = wave_max(r3);
-        b = __any(b != 0u) ? 1u : 0u;
-        if (threadIdx.x == 0) {
-            DevState s = a.st[a.par];
-            if (step_open(s)) {
-                const double r[4] = {r0, r1, r2, r3};
-                if (b != 0u || !(finite_t(r0) && finite_t(r1) && finite_t(r2) && finite_t(r3))) {
-                    s.bad = 1;
-                    s.active = 0;
-                } else {
-                    plan_step(s, a.ham, a.hpD, a.dim, a.ihxD, a.ihyD, r);
-                    s.active = s.bad ? 0 : 1;
-                }
-            } else {
-                s.active = 0;   // nothing to do: carry the record over unchanged
-            }
-            s_plan = s;
-            if (blockIdx.x == 0) a.st[a.par ^ 1] = s;
-        }
-    }
-    __syncthreads();
-    dt = s_plan.dt;
-    ax = s_plan.alpha_x;
-    ay = s_plan.alpha_y;
-    return s_plan.active != 0;
-}
-
-// Third stage, workgroup 0: empty the slots for the next step's first stage.
-template <typename T, typename P>
-__device__ inline void clear_slots(const StageArgs<T, P>& a) {
-    if (blockIdx.x == 0 && threadIdx.x < kSlots) {
-        RangeSlots* sl = static_cast<RangeSlots*>(a.slots);
-        const int k = threadIdx.x;
-        sl->key[0][k] = ~0ull;
-        sl->key[1][k] = 0ull;
-        sl->key[2][k] = ~0ull;
-        sl->key[3][k] = 0ull;
-        sl->bad[k] = 0u;
-    }
-}
-
-// Entry of a stage kernel: whether this workgroup has work, and the step's dt and
-// dissipation for the second and third stages.
-template <int STAGE, typename T, typename P>
-__device__ inline bool stage_entry(const StageArgs<T, P>& a, double& dt, double& ax,
-                                   double& ay) {
-    dt = ax = ay = 0.0;
-    if (STAGE == kStagePre) return step_open(a.st[a.par]);
-    if (STAGE == kStageMid) return plan_in_block(a, dt, ax, ay);
-    if (STAGE == kStageLast) {
-        const DevState& n = a.st[a.par ^ 1];
-        if (!n.active) return false;
-        dt = n.dt;
-        ax = n.alpha_x;
-        ay = n.alpha_y;
-        clear_slots(a);
-        return true;
-    }
-    return true;
-}
-
-// 2 (TX / SX) TY threads: row threads and column threads (16 TY for 64-wide tiles).
-template <typename T, typename P, int STAGE, int TY>
-__global__ __launch_bounds__(16 * TY) void k_stage2d(StageArgs<T, P> a) {
-    using TL = Tile<T, P, kTX, TY, kSX, kSY>;
-    static_assert(TL::kThreads == 16 * TY, "launch bounds");
-    constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
-    __shared__ P phiL[TL::kPhiElems];
-    __shared__ T uL[TL::kUElems];
-    __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
-    const int nb = a.nbx * a.nby;
-    const int tile = tile_of_block(blockIdx.x, nb, a.remap);
-    const int64_t x0 = int64_t(tile % a.nbx) * kTX;
-    const int64_t y0 = int64_t(tile / a.nbx) * TY;
-    const int tid = threadIdx.x;
-    double dt, ax, ay;
-    if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
-        // issue the tile's loads before the step plan so that their latencies overlap
-        typename TL::Gathered gth;
-        TL::gather(tid, a, x0, y0, phiL, pnL, gth);
-        if (!stage_entry<STAGE>(a, dt, ax, ay)) return;   // uniform over the workgroup
-        TL::make_phi1(tid, a, dt, ax, ay, phiL, gth);
-    } else {
-        if (!stage_entry<STAGE>(a, dt, ax, ay)) return;
-        TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
-    }
-    __syncthreads();
-    T vm[kSY], vp[kSY];
-    const bool rows = tid < TL::kHalf;   // wave-uniform: the first half of the waves march rows
-    if (rows)
-        TL::sweep_x(tid, a, phiL, uL);
-    else
-        TL::sweep_y(tid - TL::kHalf, a, phiL, vm, vp);
-    __syncthreads();
-    Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
-    if (!rows) TL::finish(tid - TL::kHalf, uL, vm, vp, phiL, kCenter ? pnL : nullptr, fin);
-
-    if (STAGE == kStagePre) {
-        fold_range<TL::kThreads / 64>(a, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad);
-    } else if (STAGE == kStageLast) {
-        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
-    }
-}
-
-template <typename T, typename P, int STAGE>
-__global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
-    using TL = Tile1D<T, P, kTX1, kS1>;
-    constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
-    __shared__ P phiL[TL::kPhiElems];
-    __shared__ T uL[TL::kUElems];
-    __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
-    double dt, ax, ay;
-    if (!stage_entry<STAGE>(a, dt, ax, ay)) return;
-    const int64_t x0 = int64_t(blockIdx.x) * kTX1;
-    const int tid = threadIdx.x;
-    TL::template load<STAGE>(tid, a, x0, dt, ax, 0.0, phiL, pnL);
-    __syncthreads();
-    TL::sweep_x(tid, a, phiL, uL);
-    __syncthreads();
-    Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
-    for (int c = tid; c < kTX1; c += 256)
-        fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], kCenter ? pnL[c] : P(0));
-    if (STAGE == kStagePre) {
-        fold_range<4>(a, fin.lo_u, fin.hi_u, T(0), T(0), fin.bad);
-    } else if (STAGE == kStageLast) {
-        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
-    }
-}
-
-__global__ void k_set_target(DevState* st, double t_final, double cfl, int64_t steps_left) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->t_final = t_final;
-        st->cfl = cfl;
-        st->steps_left = steps_left;
-        st->active = 0;
-    }
-}
-
-// Both step records to t = 0 and empty range slots.
-__global__ void k_reset(DevState* st, RangeSlots* sl) {
-    if (blockIdx.x == 0 && threadIdx.x < 2) {
-        DevState s;
-        s.t = 0.0;
-        s.t_final = 0.0;
-        s.cfl = 0.0;
-        s.dt = 0.0;
-        s.alpha_x = 0.0;
-        s.alpha_y = 0.0;
-        for (int k = 0; k < 4; ++k) s.range[k] = 0.0;
-        s.steps = 0;
-        s.steps_left = 0;
-        s.active = 0;
-        s.bad = 0;
-        s.pad[0] = s.pad[1] = 0;
-        st[threadIdx.x] = s;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < kSlots) {
-        const int k = threadIdx.x;
-        sl->key[0][k] = ~0ull;
-        sl->key[1][k] = 0ull;
-        sl->key[2][k] = ~0ull;
-        sl->key[3][k] = 0ull;
-        sl->bad[k] = 0u;
-    }
-}
-
-__global__ void k_d2f(const double* in, float* out, int64_t n) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x)
-        out[i] = float(in[i]);
-}
-
-__global__ void k_f2d(const float* in, double* out, int64_t n) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x)
-        out[i] = double(in[i]);
-}
-
-__global__ void k_check_finite(const double* in, int64_t n, DevState* st) {
-    int bad = 0;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += int64_t(gridDim.x) * blockDim.x)
-        if (!finite_t(in[i])) bad = 1;
-    if (__syncthreads_or(bad) && threadIdx.x == 0) st->bad = 1;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -611,13 +313,13 @@ hjw_status check_ready(const hjw_grid* g) {
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
-const char* hjw_last_error(void) { return g_last_error.c_str(); }
+const char* hjw_last_error(void) { return hjw::last_error().c_str(); }
 
 const char* hjw_version(void) { return "hjw 0.1 (WENO-L, gfx950)"; }
 
 hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const double* hi,
                            const int* bc, int prec, hjw_grid** out) {
-    g_last_error.clear();
+    hjw::last_error().clear();
     if (!out) return fail(HJW_EINVAL, "out is NULL");
     *out = nullptr;
     if (dim != 1 && dim != 2) return fail(HJW_EINVAL, "dim must be 1 or 2 (got %d)", dim);

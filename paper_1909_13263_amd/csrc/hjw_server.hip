@@ -1,0 +1,687 @@
+// hjw_server.hip - continuous batching of many WENO-L solves on one GPU.
+//
+// Every admitted solve keeps phi, its stage buffer, its flux records, two step
+// records and its range slots resident in HBM.  A batched step is the three stage
+// kernels of one RK3 step (hjw_kernels.h) launched once over the tiles of all
+// admitted solves: a device-resident table gives each solve's arguments and first
+// tile, and each workgroup finds its solve by binary search.  Each solve keeps its own
+// dissipation and time step; solves past their t_final exit at once.  Between
+// chunks of batched steps the host retires finished solves (phi to host memory,
+// pool space released) and admits waiting requests first-in first-out.  Chunks are
+// replayed from HIP graphs cached by launch size, so admission and retirement only
+// rewrite the table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "hjw.h"
+#include "hjw_common.h"
+#include "hjw_kernels.h"
+
+namespace hjw {
+
+// One batched launch of a stage over all admitted solves.  table[g] holds solve g's
+// arguments with the parity it has when flip is 0; tile_start[g] is its first tile
+// (tile_start[ngrids] = total tiles).  Workgroups past the last tile exit.
+template <typename T, typename P, int STAGE>
+__global__ __launch_bounds__(256) void k_stage2d_batch(const StageArgs<T, P>* table,
+                                                      const int* tile_start, const int* ngrids,
+                                                      int flip) {
+    const int ng = *ngrids;
+    const int b = int(blockIdx.x);
+    if (ng <= 0 || b >= tile_start[ng]) return;
+    int lo = 0, hi = ng;  // tile_start[lo] <= b < tile_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    StageArgs<T, P> a = table[lo];
+    a.par ^= flip;
+    // the second stage writes phi_2, the third phi^{n+1} over phi^n
+    if (STAGE == kStageMid) a.out = const_cast<P*>(a.phi_s);
+    if (STAGE == kStageLast) a.out = const_cast<P*>(a.phi_n);
+    stage_tile2d<T, P, STAGE, 16>(a, b - tile_start[lo]);
+}
+
+// A newly admitted solve: record 0 is current (t = 0, target t_final), slots empty.
+__global__ void k_admit(DevState* st, RangeSlots* sl, double t_final, double cfl) {
+    if (threadIdx.x < 2) {
+        DevState s;
+        s.t = 0.0;
+        s.t_final = t_final;
+        s.cfl = cfl;
+        s.dt = 0.0;
+        s.alpha_x = 0.0;
+        s.alpha_y = 0.0;
+        for (int k = 0; k < 4; ++k) s.range[k] = 0.0;
+        s.steps = 0;
+        s.steps_left = INT64_MAX;
+        s.active = 0;
+        s.bad = 0;
+        s.pad[0] = s.pad[1] = 0;
+        st[threadIdx.x] = s;
+    }
+    if (threadIdx.x < kSlots) {
+        const int k = threadIdx.x;
+        sl->key[0][k] = ~0ull;
+        sl->key[1][k] = 0ull;
+        sl->key[2][k] = ~0ull;
+        sl->key[3][k] = 0ull;
+        sl->bad[k] = 0u;
+    }
+}
+
+}  // namespace hjw
+
+using namespace hjw;
+
+namespace {
+
+constexpr int kChunkSteps = 8;    // batched steps per chunk (even: replays keep the parity)
+constexpr int kTileBucket = 128;  // smallest launch, in tiles
+constexpr size_t kGraphCache = 12;
+constexpr int kTY = 16;
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// First-fit allocator over [0, size) in 256-byte units, coalescing on release.
+class PoolMap {
+public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    size_t alloc(size_t bytes) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t bytes) {
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Req {
+    int64_t id = 0;
+    hjw_request r{};
+    std::vector<double> phi0;
+    double t_submit = 0.0, t_finish = 0.0;
+    int state = 0;  // 0 queued, 1 admitted, 2 finished
+    hjw_status status = HJW_OK;
+    std::vector<double> result;
+    hjw_info info{};
+    size_t off = 0, bytes = 0;
+    int slot = -1, tiles = 0, par0 = 0;
+    int64_t cells = 0, steps_seen = 0;
+};
+
+struct GraphEntry {
+    int tiles;
+    int flip;
+    hipGraphExec_t exec;
+    uint64_t used;
+};
+
+size_t elem_phi(int prec) { return prec == HJW_FP32 ? 4 : 8; }
+size_t elem_flux(int prec) { return prec == HJW_FP64 ? 8 : 4; }
+
+size_t footprint(int prec, const hjw_request& r) {
+    const size_t n = size_t(r.n[0]) * size_t(r.n[1]);
+    return 2 * align256(n * elem_phi(prec)) + align256(std::max(3 * n * elem_flux(prec), 8 * n));
+}
+
+size_t entry_bytes(int prec) {
+    switch (prec) {
+    case HJW_FP64:
+        return sizeof(StageArgs<double, double>);
+    case HJW_FP32_MIXED:
+        return sizeof(StageArgs<float, double>);
+    default:
+        return sizeof(StageArgs<float, float>);
+    }
+}
+
+hjw_status validate(const hjw_request& r) {
+    for (int d = 0; d < 2; ++d) {
+        if (r.n[d] < 8 || r.n[d] > (int64_t(1) << 20))
+            return fail(HJW_EINVAL, "request axis %d: n = %lld out of range", d,
+                        (long long)r.n[d]);
+        if (!(r.hi[d] > r.lo[d]) || !std::isfinite(r.lo[d]) || !std::isfinite(r.hi[d]))
+            return fail(HJW_EINVAL, "request axis %d: need finite lo < hi", d);
+        if (r.bc[d] != HJW_BC_PERIODIC && r.bc[d] != HJW_BC_EXTRAP)
+            return fail(HJW_EINVAL, "request axis %d: unknown boundary %d", d, r.bc[d]);
+    }
+    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_NORM)
+        return fail(HJW_EINVAL, "unknown Hamiltonian %d", r.ham);
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(r.params[k])) return fail(HJW_EINVAL, "non-finite parameter");
+    if (r.ham == HJW_H_NORM && r.params[1] < 0.0) return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    if (!std::isfinite(r.t_final) || r.t_final < 0.0 || !(r.cfl > 0.0) || !std::isfinite(r.cfl))
+        return fail(HJW_EINVAL, "need finite t_final >= 0 and cfl > 0");
+    return HJW_OK;
+}
+
+}  // namespace
+
+struct hjw_server {
+    int prec = HJW_FP32_MIXED;
+    char* base = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int max_active = 0;
+
+    // control area at the head of the pool
+    void* d_table = nullptr;
+    int* d_tile_start = nullptr;
+    int* d_ngrids = nullptr;
+    DevState* d_states = nullptr;   // 2 records per slot
+    RangeSlots* d_slots = nullptr;
+    // pinned mirrors
+    char* h_table = nullptr;
+    int* h_tile_start = nullptr;
+    int* h_ngrids = nullptr;
+    DevState* h_states = nullptr;
+
+    size_t heap_off = 0, heap_bytes = 0, in_use = 0, peak = 0;
+    PoolMap heap;
+    std::vector<int> free_slots;
+    std::deque<int64_t> queue;
+    std::vector<int64_t> active;  // table order
+    std::unordered_map<int64_t, Req> reqs;
+    std::vector<int64_t> completed;
+    int64_t next_id = 1;
+    int flip = 0;
+    bool table_dirty = true;
+    int launch_tiles = 0;
+    std::vector<GraphEntry> graphs;
+    uint64_t use_clock = 0;
+    hjw_server_stats stats{};
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+};
+
+namespace {
+
+// Launch sizes: the total tile count rounded up to one of eight steps per octave (at
+// least kTileBucket), so that few graphs cover every mix and at most 1/8 of the
+// workgroups of a launch find no tile.
+int launch_size(int tiles) {
+    if (tiles <= kTileBucket) return kTileBucket;
+    int step = kTileBucket;
+    while (step * 16 <= tiles) step *= 2;   // step = 2^floor(log2 tiles) / 8, >= kTileBucket
+    return (tiles + step - 1) / step * step;
+}
+
+template <typename T, typename P>
+StageArgs<T, P> request_args(const hjw_server* s, const Req& q) {
+    const hjw_request& r = q.r;
+    const size_t n = size_t(q.cells);
+    char* w = s->base + s->heap_off + q.off;
+    StageArgs<T, P> a{};
+    a.phi_n = reinterpret_cast<const P*>(w);
+    a.phi_s = reinterpret_cast<const P*>(w + align256(n * sizeof(P)));
+    a.out = nullptr;  // chosen per stage by the batched kernel
+    a.flux = reinterpret_cast<T*>(w + 2 * align256(n * sizeof(P)));
+    a.st = s->d_states + 2 * q.slot;
+    a.par = q.par0;
+    a.slots = s->d_slots + q.slot;
+    a.nx = r.n[0];
+    a.ny = r.n[1];
+    a.bcx = r.bc[0];
+    a.bcy = r.bc[1];
+    const double dx = (r.hi[0] - r.lo[0]) / double(r.n[0]);
+    const double dy = (r.hi[1] - r.lo[1]) / double(r.n[1]);
+    a.ihx = P(1.0 / dx);
+    a.ihy = P(1.0 / dy);
+    a.ihxT = T(1.0 / dx);
+    a.ihyT = T(1.0 / dy);
+    a.epsx = T(4.0 * kEps / (dx * dx));
+    a.epsy = T(4.0 * kEps / (dy * dy));
+    a.ham = r.ham;
+    for (int k = 0; k < 4; ++k) {
+        a.hpT[k] = T(r.params[k]);
+        a.hpD[k] = r.params[k];
+    }
+    a.ihxD = 1.0 / dx;
+    a.ihyD = 1.0 / dy;
+    a.nbx = int((r.n[0] + kTX - 1) / kTX);
+    a.nby = int((r.n[1] + kTY - 1) / kTY);
+    a.remap = 0;
+    a.dim = 2;
+    return a;
+}
+
+template <typename T, typename P>
+void write_table(hjw_server* s) {
+    StageArgs<T, P>* tab = reinterpret_cast<StageArgs<T, P>*>(s->h_table);
+    int tiles = 0;
+    for (size_t g = 0; g < s->active.size(); ++g) {
+        const Req& q = s->reqs.at(s->active[g]);
+        tab[g] = request_args<T, P>(s, q);
+        s->h_tile_start[g] = tiles;
+        tiles += q.tiles;
+    }
+    s->h_tile_start[s->active.size()] = tiles;
+    *s->h_ngrids = int(s->active.size());
+    s->launch_tiles = launch_size(tiles);
+}
+
+template <typename T, typename P>
+hipError_t launch_batched_step(hjw_server* s, int flip) {
+    const StageArgs<T, P>* tab = static_cast<const StageArgs<T, P>*>(s->d_table);
+    const dim3 grid(unsigned(std::max(1, s->launch_tiles))), block(256);
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre>), grid, block, 0, s->stream, tab,
+                       s->d_tile_start, s->d_ngrids, flip);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageMid>), grid, block, 0, s->stream, tab,
+                       s->d_tile_start, s->d_ngrids, flip);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageLast>), grid, block, 0, s->stream, tab,
+                       s->d_tile_start, s->d_ngrids, flip);
+    return hipGetLastError();
+}
+
+hipError_t batched_step(hjw_server* s, int flip) {
+    switch (s->prec) {
+    case HJW_FP64:
+        return launch_batched_step<double, double>(s, flip);
+    case HJW_FP32_MIXED:
+        return launch_batched_step<float, double>(s, flip);
+    default:
+        return launch_batched_step<float, float>(s, flip);
+    }
+}
+
+void rebuild_table(hjw_server* s) {
+    switch (s->prec) {
+    case HJW_FP64:
+        write_table<double, double>(s);
+        break;
+    case HJW_FP32_MIXED:
+        write_table<float, double>(s);
+        break;
+    default:
+        write_table<float, float>(s);
+    }
+}
+
+hjw_status upload_table(hjw_server* s) {
+    rebuild_table(s);
+    const size_t ng = s->active.size();
+    if (ng)
+        HIP_TRY(hipMemcpyAsync(s->d_table, s->h_table, ng * entry_bytes(s->prec),
+                               hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->d_tile_start, s->h_tile_start, (ng + 1) * sizeof(int),
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->d_ngrids, s->h_ngrids, sizeof(int), hipMemcpyHostToDevice,
+                           s->stream));
+    s->table_dirty = false;
+    return HJW_OK;
+}
+
+hjw_status admit(hjw_server* s) {
+    bool any = false;
+    while (!s->queue.empty() && !s->free_slots.empty()) {
+        Req& q = s->reqs.at(s->queue.front());
+        const size_t off = s->heap.alloc(q.bytes);
+        if (off == SIZE_MAX) break;  // first in, first out: wait for space
+        q.off = off;
+        q.slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        q.par0 = s->flip;  // its record 0 is current at the next launch
+        q.state = 1;
+        q.steps_seen = 0;
+        s->in_use += q.bytes;
+        s->peak = std::max(s->peak, s->in_use);
+        const size_t n = size_t(q.cells);
+        char* w = s->base + s->heap_off + q.off;
+        if (s->prec == HJW_FP32) {
+            double* stage = reinterpret_cast<double*>(w + 2 * align256(n * 4));
+            HIP_TRY(hipMemcpyAsync(stage, q.phi0.data(), n * sizeof(double),
+                                   hipMemcpyHostToDevice, s->stream));
+            hipLaunchKernelGGL(k_d2f, dim3(256), dim3(256), 0, s->stream, stage,
+                               reinterpret_cast<float*>(w), int64_t(n));
+            HIP_TRY(hipGetLastError());
+        } else {
+            HIP_TRY(hipMemcpyAsync(w, q.phi0.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                                   s->stream));
+        }
+        hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, s->stream, s->d_states + 2 * q.slot,
+                           s->d_slots + q.slot, q.r.t_final, q.r.cfl);
+        HIP_TRY(hipGetLastError());
+        s->active.push_back(q.id);
+        s->queue.pop_front();
+        s->table_dirty = true;
+        any = true;
+    }
+    if (s->table_dirty) {
+        hjw_status st = upload_table(s);
+        if (st != HJW_OK) return st;
+        any = true;
+    }
+    // the host mirrors and phi0 buffers are reused only after their copies are done
+    if (any) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        for (int64_t id : s->active) std::vector<double>().swap(s->reqs.at(id).phi0);
+    }
+    return HJW_OK;
+}
+
+void drop_graphs(hjw_server* s) {
+    for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.exec);
+    s->graphs.clear();
+}
+
+hjw_status run_chunk(hjw_server* s) {
+    // a cached graph of kChunkSteps batched steps for this launch size and parity
+    GraphEntry* ge = nullptr;
+    for (auto& g : s->graphs)
+        if (g.tiles == s->launch_tiles && g.flip == s->flip) ge = &g;
+    if (!ge) {
+        if (s->graphs.size() >= kGraphCache) {
+            auto lru = std::min_element(s->graphs.begin(), s->graphs.end(),
+                                        [](const GraphEntry& a, const GraphEntry& b) {
+                                            return a.used < b.used;
+                                        });
+            (void)hipGraphExecDestroy(lru->exec);
+            s->graphs.erase(lru);
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed));
+        hipError_t e = hipSuccess;
+        int f = s->flip;
+        for (int k = 0; k < kChunkSteps && e == hipSuccess; ++k, f ^= 1) e = batched_step(s, f);
+        const hipError_t e2 = hipStreamEndCapture(s->stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(HJW_EHIP, "batched graph capture failed: %s / %s", hipGetErrorString(e),
+                        hipGetErrorString(e2));
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess)
+            return fail(HJW_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e3));
+        s->graphs.push_back(GraphEntry{s->launch_tiles, s->flip, exec, 0});
+        ge = &s->graphs.back();
+    }
+    ge->used = ++s->use_clock;
+    HIP_TRY(hipGraphLaunch(ge->exec, s->stream));
+    s->stats.batched_steps += kChunkSteps;  // kChunkSteps is even: the parity is unchanged
+    return HJW_OK;
+}
+
+hjw_status retire(hjw_server* s) {
+    const size_t nrec = 2 * size_t(s->max_active);
+    HIP_TRY(hipMemcpyAsync(s->h_states, s->d_states, nrec * sizeof(DevState),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::vector<int64_t> keep;
+    keep.reserve(s->active.size());
+    bool any = false;
+    for (int64_t id : s->active) {
+        Req& q = s->reqs.at(id);
+        const DevState& rec = s->h_states[2 * q.slot + (q.par0 ^ s->flip)];
+        s->stats.node_stages += 3.0 * double(q.cells) * double(rec.steps - q.steps_seen);
+        q.steps_seen = rec.steps;
+        const bool bad = rec.bad != 0;
+        if (!bad && rec.t < q.r.t_final) {
+            keep.push_back(id);
+            continue;
+        }
+        any = true;
+        q.info.steps = rec.steps;
+        q.info.t = rec.t;
+        q.info.last_dt = rec.dt;
+        q.info.alpha_x = rec.alpha_x;
+        q.info.alpha_y = rec.alpha_y;
+        for (int k = 0; k < 4; ++k) q.info.range[k] = rec.range[k];
+        q.status = bad ? HJW_ENONFINITE : HJW_OK;
+        const size_t n = size_t(q.cells);
+        char* w = s->base + s->heap_off + q.off;
+        if (!bad) {
+            q.result.resize(n);
+            const void* src = w;
+            if (s->prec == HJW_FP32) {
+                double* stage = reinterpret_cast<double*>(w + 2 * align256(n * 4));
+                hipLaunchKernelGGL(k_f2d, dim3(256), dim3(256), 0, s->stream,
+                                   reinterpret_cast<const float*>(w), stage, int64_t(n));
+                HIP_TRY(hipGetLastError());
+                src = stage;
+            }
+            HIP_TRY(hipMemcpyAsync(q.result.data(), src, n * sizeof(double),
+                                   hipMemcpyDeviceToHost, s->stream));
+        }
+        q.state = 2;
+        s->completed.push_back(id);
+        if (bad)
+            s->stats.failed += 1;
+        else
+            s->stats.done += 1;
+    }
+    if (any) {
+        HIP_TRY(hipStreamSynchronize(s->stream));  // results copied before space is reused
+        const double now = seconds_since(s->t0);
+        for (int64_t id : s->active) {
+            Req& q = s->reqs.at(id);
+            if (q.state != 2) continue;
+            q.t_finish = now;
+            s->heap.release(q.off, q.bytes);
+            s->in_use -= q.bytes;
+            s->free_slots.push_back(q.slot);
+            q.slot = -1;
+        }
+        s->active.swap(keep);
+        s->table_dirty = true;
+    }
+    return HJW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjw_status hjw_server_footprint(int prec, const hjw_request* req, size_t* bytes) {
+    if (!req || !bytes) return fail(HJW_EINVAL, "NULL argument");
+    if (prec < HJW_FP64 || prec > HJW_FP32) return fail(HJW_EINVAL, "unknown precision %d", prec);
+    hjw_status st = validate(*req);
+    if (st != HJW_OK) return st;
+    *bytes = footprint(prec, *req);
+    return HJW_OK;
+}
+
+hjw_status hjw_server_create(int prec, void* pool, size_t pool_bytes, int max_active,
+                             void* stream, hjw_server** out) {
+    hjw::last_error().clear();
+    if (!out || !pool) return fail(HJW_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (prec < HJW_FP64 || prec > HJW_FP32) return fail(HJW_EINVAL, "unknown precision %d", prec);
+    if (max_active < 1 || max_active > 1024) return fail(HJW_EINVAL, "max_active must be 1..1024");
+    if (reinterpret_cast<uintptr_t>(pool) % 256 != 0)
+        return fail(HJW_EINVAL, "pool must be 256-byte aligned");
+    const size_t ctl = align256(size_t(max_active) * entry_bytes(prec)) +
+                       align256(size_t(max_active + 1) * sizeof(int)) + align256(sizeof(int)) +
+                       align256(2 * size_t(max_active) * sizeof(DevState)) +
+                       align256(size_t(max_active) * sizeof(RangeSlots));
+    if (pool_bytes < ctl + 4096) return fail(HJW_ENOMEM, "pool too small for %d slots", max_active);
+    hjw_server* s = new (std::nothrow) hjw_server();
+    if (!s) return fail(HJW_ENOMEM, "host allocation failed");
+    s->prec = prec;
+    s->base = static_cast<char*>(pool);
+    s->bytes = pool_bytes;
+    s->max_active = max_active;
+    size_t o = 0;
+    s->d_table = s->base + o;
+    o += align256(size_t(max_active) * entry_bytes(prec));
+    s->d_tile_start = reinterpret_cast<int*>(s->base + o);
+    o += align256(size_t(max_active + 1) * sizeof(int));
+    s->d_ngrids = reinterpret_cast<int*>(s->base + o);
+    o += align256(sizeof(int));
+    s->d_states = reinterpret_cast<DevState*>(s->base + o);
+    o += align256(2 * size_t(max_active) * sizeof(DevState));
+    s->d_slots = reinterpret_cast<RangeSlots*>(s->base + o);
+    o += align256(size_t(max_active) * sizeof(RangeSlots));
+    s->heap_off = o;
+    s->heap_bytes = pool_bytes - o;
+    s->heap.reset(s->heap_bytes / 256 * 256);
+    for (int k = max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
+    hjw_status st = HJW_OK;
+    s->stream = static_cast<hipStream_t>(stream);
+    if (!s->stream) {
+        if (hipStreamCreate(&s->stream) != hipSuccess) st = fail(HJW_EHIP, "hipStreamCreate failed");
+        s->own_stream = true;
+    }
+    if (st == HJW_OK &&
+        (hipHostMalloc(reinterpret_cast<void**>(&s->h_table), size_t(max_active) * entry_bytes(prec),
+                       hipHostMallocDefault) != hipSuccess ||
+         hipHostMalloc(reinterpret_cast<void**>(&s->h_tile_start), size_t(max_active + 1) * sizeof(int),
+                       hipHostMallocDefault) != hipSuccess ||
+         hipHostMalloc(reinterpret_cast<void**>(&s->h_ngrids), sizeof(int), hipHostMallocDefault) !=
+             hipSuccess ||
+         hipHostMalloc(reinterpret_cast<void**>(&s->h_states), 2 * size_t(max_active) * sizeof(DevState),
+                       hipHostMallocDefault) != hipSuccess))
+        st = fail(HJW_EHIP, "hipHostMalloc failed");
+    if (st == HJW_OK) {
+        *s->h_ngrids = 0;
+        s->h_tile_start[0] = 0;
+        st = upload_table(s);
+    }
+    if (st == HJW_OK && hipStreamSynchronize(s->stream) != hipSuccess)
+        st = fail(HJW_EHIP, "hipStreamSynchronize failed");
+    if (st != HJW_OK) {
+        hjw_server_destroy(s);
+        return st;
+    }
+    s->stats.pool_bytes = s->heap_bytes;
+    *out = s;
+    return HJW_OK;
+}
+
+hjw_status hjw_server_submit(hjw_server* s, const hjw_request* req, const double* phi0,
+                             int64_t* id) {
+    if (!s || !req || !phi0 || !id) return fail(HJW_EINVAL, "NULL argument");
+    hjw_status st = validate(*req);
+    if (st != HJW_OK) return st;
+    const size_t bytes = footprint(s->prec, *req);
+    if (bytes > s->heap_bytes)
+        return fail(HJW_ENOMEM, "request needs %zu pool bytes, the pool has %zu", bytes,
+                    s->heap_bytes);
+    const int64_t n = req->n[0] * req->n[1];
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(phi0[k])) return fail(HJW_ENONFINITE, "phi0 holds non-finite values");
+    Req q;
+    q.id = s->next_id++;
+    q.r = *req;
+    q.phi0.assign(phi0, phi0 + n);
+    q.t_submit = seconds_since(s->t0);
+    q.bytes = bytes;
+    q.cells = n;
+    q.tiles = int(((req->n[0] + kTX - 1) / kTX) * ((req->n[1] + kTY - 1) / kTY));
+    *id = q.id;
+    s->queue.push_back(q.id);
+    s->reqs.emplace(q.id, std::move(q));
+    s->stats.submitted += 1;
+    return HJW_OK;
+}
+
+hjw_status hjw_server_run(hjw_server* s, int chunks, int64_t* active, int64_t* queued) {
+    if (!s) return fail(HJW_EINVAL, "NULL server");
+    hjw_status st = admit(s);
+    for (int c = 0; st == HJW_OK && c < chunks && !s->active.empty(); ++c) {
+        st = run_chunk(s);
+        if (st == HJW_OK) st = retire(s);
+        if (st == HJW_OK) st = admit(s);
+    }
+    if (active) *active = int64_t(s->active.size());
+    if (queued) *queued = int64_t(s->queue.size());
+    return st;
+}
+
+hjw_status hjw_server_completed(hjw_server* s, int64_t* ids, int cap, int* count) {
+    if (!s || !count || (cap > 0 && !ids)) return fail(HJW_EINVAL, "NULL argument");
+    const int n = std::min<int>(cap, int(s->completed.size()));
+    for (int k = 0; k < n; ++k) ids[k] = s->completed[k];
+    s->completed.erase(s->completed.begin(), s->completed.begin() + n);
+    *count = n;
+    return HJW_OK;
+}
+
+hjw_status hjw_server_result(hjw_server* s, int64_t id, double* phi_out, hjw_info* info,
+                             double* t_submit, double* t_finish) {
+    if (!s) return fail(HJW_EINVAL, "NULL server");
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(HJW_EINVAL, "unknown request %lld", (long long)id);
+    Req& q = it->second;
+    if (q.state != 2) return fail(HJW_ESTATE, "request %lld is not finished", (long long)id);
+    if (phi_out && !q.result.empty()) std::memcpy(phi_out, q.result.data(), q.result.size() * 8);
+    if (info) *info = q.info;
+    if (t_submit) *t_submit = q.t_submit;
+    if (t_finish) *t_finish = q.t_finish;
+    const hjw_status st = q.status;
+    s->reqs.erase(it);
+    if (st != HJW_OK) return fail(st, "request %lld produced non-finite values", (long long)id);
+    return HJW_OK;
+}
+
+hjw_status hjw_server_get_stats(const hjw_server* s, hjw_server_stats* out) {
+    if (!s || !out) return fail(HJW_EINVAL, "NULL argument");
+    *out = s->stats;
+    out->queued = int64_t(s->queue.size());
+    out->active = int64_t(s->active.size());
+    out->pool_in_use = s->in_use;
+    out->pool_peak = s->peak;
+    return HJW_OK;
+}
+
+double hjw_server_clock(const hjw_server* s) { return s ? seconds_since(s->t0) : 0.0; }
+
+void hjw_server_destroy(hjw_server* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    if (s->h_table) (void)hipHostFree(s->h_table);
+    if (s->h_tile_start) (void)hipHostFree(s->h_tile_start);
+    if (s->h_ngrids) (void)hipHostFree(s->h_ngrids);
+    if (s->h_states) (void)hipHostFree(s->h_states);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+}  // extern "C"

@@ -39,6 +39,21 @@ class _Info(ctypes.Structure):
                 ("range", ctypes.c_double * 4)]
 
 
+class _Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64 * 2), ("lo", ctypes.c_double * 2),
+                ("hi", ctypes.c_double * 2), ("bc", ctypes.c_int * 2), ("ham", ctypes.c_int),
+                ("params", ctypes.c_double * 4), ("t_final", ctypes.c_double),
+                ("cfl", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("done", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("batched_steps", ctypes.c_int64), ("node_stages", ctypes.c_double),
+                ("pool_bytes", ctypes.c_size_t), ("pool_in_use", ctypes.c_size_t),
+                ("pool_peak", ctypes.c_size_t)]
+
+
 @dataclass
 class Info:
     steps: int
@@ -77,6 +92,20 @@ def lib():
             "hjw_kernel_times": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
             "hjw_time_kernels": (ctypes.c_int, [vp, ctypes.c_int, dp]),
             "hjw_grid_destroy": (None, [vp]),
+            "hjw_server_footprint": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_Request),
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
+            "hjw_server_create": (ctypes.c_int, [ctypes.c_int, vp, ctypes.c_size_t, ctypes.c_int,
+                                                 vp, ctypes.POINTER(vp)]),
+            "hjw_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(_Request), dp,
+                                                 ctypes.POINTER(i64)]),
+            "hjw_server_run": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(i64),
+                                              ctypes.POINTER(i64)]),
+            "hjw_server_completed": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.c_int,
+                                                    ctypes.POINTER(ctypes.c_int)]),
+            "hjw_server_result": (ctypes.c_int, [vp, i64, dp, ctypes.POINTER(_Info), dp, dp]),
+            "hjw_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(_ServerStats)]),
+            "hjw_server_clock": (ctypes.c_double, [vp]),
+            "hjw_server_destroy": (None, [vp]),
             "hjw_last_error": (ctypes.c_char_p, []),
             "hjw_version": (ctypes.c_char_p, []),
         }
@@ -215,3 +244,140 @@ def grid_for(problem, prec=FP64, **kw) -> Grid:
     g = Grid(problem.shape, problem.lo, problem.hi, problem.bc, prec, **kw)
     g.set_hamiltonian(problem.ham, problem.params)
     return g
+
+
+def _request(problem, shape=None) -> _Request:
+    """The C request record of a 2-D workloads.Problem."""
+    if len(problem.shape) != 2:
+        raise ValueError("the server takes 2-D problems")
+    r = _Request()
+    ny, nx = problem.shape
+    r.n[0], r.n[1] = nx, ny
+    for d in range(2):
+        r.lo[d] = float(problem.lo[d])
+        r.hi[d] = float(problem.hi[d])
+    bcs = problem.bc if isinstance(problem.bc, (tuple, list)) else (problem.bc,) * 2
+    r.bc[0], r.bc[1] = int(bcs[0]), int(bcs[1])
+    r.ham = int(problem.ham)
+    params = [float(v) for v in problem.params] + [0.0] * (4 - len(problem.params))
+    for k in range(4):
+        r.params[k] = params[k]
+    r.t_final = float(problem.t_final)
+    r.cfl = float(problem.cfl)
+    return r
+
+
+@dataclass
+class Result:
+    rid: int
+    status: int
+    phi: np.ndarray | None
+    info: Info
+    t_submit: float
+    t_finish: float
+
+    @property
+    def latency(self):
+        return self.t_finish - self.t_submit
+
+
+class Server:
+    """Continuous batching of many 2-D solves over one device pool (hjw_server_*).
+
+    pool: a CUDA uint8 tensor (allocated here when None, pool_bytes long)."""
+
+    def __init__(self, prec=FP32_MIXED, pool_bytes=1 << 30, max_active=256, pool=None,
+                 stream=None):
+        import torch
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
+        self.prec = prec
+        if pool is None:
+            pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        self._pool = pool
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        torch.cuda.current_stream().synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().hjw_server_create(int(prec), ctypes.c_void_p(pool.data_ptr()),
+                                       ctypes.c_size_t(pool.numel()), int(max_active),
+                                       ctypes.c_void_p(s), ctypes.byref(h)))
+        self._h = h
+        self._shapes = {}
+
+    @staticmethod
+    def footprint(problem, prec=FP32_MIXED) -> int:
+        if isinstance(prec, str):
+            prec = PREC_NAMES[prec]
+        r = _request(problem)
+        out = ctypes.c_size_t()
+        _check(lib().hjw_server_footprint(int(prec), ctypes.byref(r), ctypes.byref(out)))
+        return int(out.value)
+
+    def submit(self, problem, phi0=None) -> int:
+        r = _request(problem)
+        a = problem.phi0() if phi0 is None else phi0
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        if a.shape != tuple(problem.shape):
+            raise ValueError(f"phi0 shape {a.shape} != {problem.shape}")
+        rid = ctypes.c_int64()
+        _check(lib().hjw_server_submit(self._h, ctypes.byref(r),
+                                       a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.byref(rid)))
+        self._shapes[int(rid.value)] = tuple(problem.shape)
+        return int(rid.value)
+
+    def run(self, chunks=1):
+        """Run up to `chunks` chunks of batched steps; returns (active, queued)."""
+        act, que = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hjw_server_run(self._h, int(chunks), ctypes.byref(act), ctypes.byref(que)))
+        return int(act.value), int(que.value)
+
+    def completed(self, cap=4096):
+        ids = (ctypes.c_int64 * cap)()
+        cnt = ctypes.c_int()
+        _check(lib().hjw_server_completed(self._h, ids, cap, ctypes.byref(cnt)))
+        return [int(ids[k]) for k in range(cnt.value)]
+
+    def result(self, rid) -> Result:
+        """Collect (and release) a finished request; a failed request has phi None."""
+        shape = self._shapes.pop(rid)
+        out = np.empty(shape, dtype=np.float64)
+        ci = _Info()
+        ts, tf = ctypes.c_double(), ctypes.c_double()
+        code = lib().hjw_server_result(self._h, int(rid),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       ctypes.byref(ci), ctypes.byref(ts), ctypes.byref(tf))
+        if code not in (OK, ENONFINITE):
+            self._shapes[rid] = shape
+            _check(code)
+        return Result(rid, code, out if code == OK else None, _info(ci), ts.value, tf.value)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().hjw_server_get_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in _ServerStats._fields_}
+
+    def clock(self) -> float:
+        return float(lib().hjw_server_clock(self._h))
+
+    def drain(self, chunks=4):
+        """Run until nothing is queued or admitted; returns the finished results."""
+        results = []
+        while True:
+            act, que = self.run(chunks)
+            for rid in self.completed():
+                results.append(self.result(rid))
+            if act == 0 and que == 0:
+                break
+        return results
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hjw_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
