@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -73,6 +75,8 @@ def parse():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0, help="16 or 32 (0: library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-vs-FP64 error of the full-size configurations")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the measured saturation rate")
@@ -142,6 +146,49 @@ def cpu_baseline(pr, seconds):
             "kind": "oracle",
             "sample": f"{steps} RK3 steps of the {pr.shape[1]}x{pr.shape[0]} grid from t=0 "
                       f"({wall:.1f} s, FP64 C, OpenMP over grid lines)"}
+
+
+def accuracy_cases():
+    """The full-size configurations whose FP32 error is reported: (label, problem, precs)."""
+    from paper_1909_13263_amd import workloads as W
+    from paper_1909_13263_amd import hjw
+    return [
+        ("burgers2d 1024^2 t=0.5/pi^2", W.burgers2d(1024, 0.5 / math.pi**2),
+         (hjw.FP32_MIXED, hjw.FP32)),
+        ("burgers2d 1024^2 t=1.5/pi^2", W.burgers2d(1024, 1.5 / math.pi**2),
+         (hjw.FP32_MIXED, hjw.FP32)),
+        ("negcos2d 2048^2 t=1.0", W.negcos2d(2048, 1.0), (hjw.FP32_MIXED,)),
+        ("levelset2d 4096^2 t=0.2", W.levelset2d(4096, 0.2), (hjw.FP32,)),
+    ]
+
+
+def solve_once(hjw, pr, prec):
+    g = hjw.grid_for(pr, prec)
+    g.set_phi(pr.phi0())
+    info = g.step_to(pr.t_final, pr.cfl)
+    phi = g.get_phi()
+    g.close()
+    return phi, info
+
+
+def accuracy(hjw):
+    """Error of the FP32 paths against FP64 on the same GPU, whose results match the
+    FP64 oracle to 1e-12 of max|phi| (the parity tests): L-inf, and L1 as the grid mean of
+    |error| (the domain-normalised integral), both also relative to max|phi|."""
+    out = {}
+    for label, pr, precs in accuracy_cases():
+        ref, info = solve_once(hjw, pr, hjw.FP64)
+        scale = float(np.abs(ref).max())
+        row = {"fp64_steps": info.steps}
+        for prec in precs:
+            phi, pinfo = solve_once(hjw, pr, prec)
+            err = np.abs(phi - ref)
+            name = {hjw.FP32_MIXED: "fp32_stencil", hjw.FP32: "fp32_storage"}[prec]
+            row[name] = {"linf": float(err.max()), "l1": float(err.mean()),
+                         "linf_rel": float(err.max()) / scale, "l1_rel": float(err.mean()) / scale,
+                         "steps": pinfo.steps}
+        out[label] = row
+    return out
 
 
 def served_stream(args, hjw):
@@ -263,6 +310,8 @@ def main():
                         "rk_steps": r["rk_steps"],
                         "kernel_ms": r["kernels"]}
         line["fp32_speedup_over_fp64"] = main_res["cell_updates_per_s"] / r["cell_updates_per_s"]
+    if not args.no_accuracy:
+        line["fp32_error_vs_fp64"] = accuracy(hjw)
     if not args.no_serve:
         line["served"] = served_stream(args, hjw)
     if not args.no_cpu_baseline:

@@ -85,8 +85,6 @@ __host__ inline double rsqrt_t(double x) { return 1.0 / std::sqrt(x); }
 __device__ inline float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __host__ inline float rcp_t(float x) { return 1.0f / x; }
 __host__ __device__ inline double rcp_t(double x) { return 1.0 / x; }
-__device__ inline float asinh_t(float x) { return asinhf(x); }
-__host__ inline float asinh_t(float x) { return std::asinh(x); }
 __device__ inline double asinh_t(double x) { return asinh(x); }
 __host__ inline double asinh_t(double x) { return std::asinh(x); }
 __device__ inline float sqrt_t(float x) { return sqrtf(x); }
@@ -142,10 +140,34 @@ __host__ __device__ inline float mean2_series(float sg, float dl, float q4) {
     return sq + sq * g2 * inner;
 }
 
-// Antiderivative of sqrt(1+s^2).
+// Antiderivative of sqrt(1+s^2): (s sqrt(1+s^2) + asinh s) / 2.
+__host__ __device__ inline double prim(double s) {
+    return 0.5 * (s * sqrt_t(1.0 + s * s) + asinh_t(s));
+}
+// FP32: from the hardware square root and base-2 logarithm (about 1 ulp each), with
+// asinh s = sign(s) ln(|s| + sqrt(1+s^2)), whose argument is >= 1 (no cancellation).
+// Only pairs with a wide relative gap use it, so that the difference of two values is
+// divided by a gap of at least tau sqrt(4 + sg^2): the rounding is amplified by a
+// small factor only.
+__device__ inline float prim(float s) {
+    const float r = __builtin_amdgcn_sqrtf(fmaf(s, s, 1.0f));
+    const float l = __builtin_amdgcn_logf(fabsf(s) + r) * 0.693147180559945309f;
+    return 0.5f * (s * r + copysignf(l, s));
+}
+__host__ inline float prim(float s) {
+    const float r = std::sqrt(std::fma(s, s, 1.0f));
+    const float l = std::log2(std::fabs(s) + r) * 0.693147180559945309f;
+    return 0.5f * (s * r + std::copysign(l, s));
+}
+
+// Quotients: exact division in FP64; in FP32 a product with the hardware reciprocal.
 template <typename T>
-__host__ __device__ inline T prim(T s) {
-    return T(0.5) * (s * sqrt_t(T(1) + s * s) + asinh_t(s));
+__host__ __device__ inline T wdiv(T num, T den) {
+    return num / den;
+}
+template <>
+__host__ __device__ inline float wdiv<float>(float num, float den) {
+    return num * rcp_t(den);
 }
 
 // Twice the means for the three pairs of one cell: (c0, b1), (c0, c1), (f0, c1).
@@ -167,9 +189,9 @@ __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA, T& MB,
     MC = mean2_series(sC, dC, qC);
     if (any_lane(wideA || wideB || wideC)) {
         const T Pc0 = prim(c0), Pb1 = prim(b1), Pc1 = prim(c1), Pf0 = prim(f0);
-        if (wideA) MA = T(2) * (Pb1 - Pc0) / dA;
-        if (wideB) MB = T(2) * (Pc1 - Pc0) / dB;
-        if (wideC) MC = T(2) * (Pc1 - Pf0) / dC;
+        if (wideA) MA = wdiv(T(2) * (Pb1 - Pc0), dA);
+        if (wideB) MB = wdiv(T(2) * (Pc1 - Pc0), dB);
+        if (wideC) MC = wdiv(T(2) * (Pc1 - Pf0), dC);
     }
 }
 
@@ -202,14 +224,6 @@ __host__ __device__ inline void weight_products(float MA, float MB, float MC, fl
     pBC = tB * tC;
 }
 
-template <typename T>
-__host__ __device__ inline T wdiv(T num, T den) {
-    return num / den;
-}
-template <>
-__host__ __device__ inline float wdiv<float>(float num, float den) {
-    return num * rcp_t(den);
-}
 
 // March along one line.  line[k*stride] is phi_s at position p0-3+k,
 // k = 0..S+5; writes phi^-(p0+k) to um[k] and phi^+(p0+k) to up[k], k < S.
