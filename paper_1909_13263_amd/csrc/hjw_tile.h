@@ -121,20 +121,23 @@ template <> struct SeriesCfg<float> { static constexpr float tau2 = 1.0e-2f; };
 //   2M = sqrt(q4) (1 + g^2 (2/3 + g^2 (2/5 (sg^2-1) + g^2 2/7 (sg^4 - 6 sg^2 + 2)))),
 //   q4 = 4 + sg^2, g = dl / q4
 // (the Taylor series of the mean about m = sg/2 with y = (h/(1+m^2))^2 = 4 g^2).
-__host__ __device__ inline double mean2_series(double sg, double dl, double q4) {
+// x receives the relative gap dl / sqrt(q4).
+__host__ __device__ inline double mean2_series(double sg, double dl, double q4, double& x) {
     const double r = rsqrt_t(q4);
     const double sq = q4 * r;
-    const double g = dl * r * r;
+    x = dl * r;
+    const double g = x * r;
     const double g2 = g * g;
     const double s2 = sg * sg;
     const double inner =
         (2.0 / 3.0) + g2 * (0.4 * (s2 - 1.0) + g2 * ((2.0 / 7.0) * (s2 * (s2 - 6.0) + 2.0)));
     return sq + sq * g2 * inner;
 }
-__host__ __device__ inline float mean2_series(float sg, float dl, float q4) {
+__host__ __device__ inline float mean2_series(float sg, float dl, float q4, float& x) {
     const float r = rsqrt_t(q4);
     const float sq = q4 * r;
-    const float g = dl * r * r;
+    x = dl * r;
+    const float g = x * r;
     const float g2 = g * g;
     const float inner = (2.0f / 3.0f) + g2 * (0.4f * (sg * sg - 1.0f));
     return sq + sq * g2 * inner;
@@ -180,18 +183,19 @@ __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA, T& MB,
     const T sB = c0 + c1, dB = c1 - c0;
     const T sC = f0 + c1, dC = c1 - f0;
     const T qA = sA * sA + T(4), qB = sB * sB + T(4), qC = sC * sC + T(4);
-    // half-gap h = dl/2 against tau sqrt(1 + m^2) = tau sqrt(q4)/2
-    const bool wideA = dA * dA >= tau2 * qA;
-    const bool wideB = dB * dB >= tau2 * qB;
-    const bool wideC = dC * dC >= tau2 * qC;
-    MA = mean2_series(sA, dA, qA);
-    MB = mean2_series(sB, dB, qB);
-    MC = mean2_series(sC, dC, qC);
-    if (any_lane(wideA || wideB || wideC)) {
+    // half-gap dl/2 against tau sqrt(1 + m^2) = tau sqrt(q4)/2: wide when x^2 >= tau^2
+    T xA, xB, xC;
+    MA = mean2_series(sA, dA, qA, xA);
+    MB = mean2_series(sB, dB, qB, xB);
+    MC = mean2_series(sC, dC, qC, xC);
+    xA *= xA;
+    xB *= xB;
+    xC *= xC;
+    if (any_lane(fmax(xA, fmax(xB, xC)) >= tau2)) {
         const T Pc0 = prim(c0), Pb1 = prim(b1), Pc1 = prim(c1), Pf0 = prim(f0);
-        if (wideA) MA = wdiv(T(2) * (Pb1 - Pc0), dA);
-        if (wideB) MB = wdiv(T(2) * (Pc1 - Pc0), dB);
-        if (wideC) MC = wdiv(T(2) * (Pc1 - Pf0), dC);
+        if (xA >= tau2) MA = wdiv(T(2) * (Pb1 - Pc0), dA);
+        if (xB >= tau2) MB = wdiv(T(2) * (Pc1 - Pc0), dB);
+        if (xC >= tau2) MC = wdiv(T(2) * (Pc1 - Pf0), dC);
     }
 }
 
@@ -261,16 +265,18 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
         weight_products(MA, MB, MC, eps4, pAB, pAC, pBC);
         const T D3a = B1 - e3;                // a - 3b + 3c - d
         const T D3b = F0 - e2;                // b - 3c + 3d - e
-        const T p6AC = T(6) * pAC;
+        // numerators and denominators below are six times those of the weighted sums
+        const T xa = pBC * D3a, xb = pAB * D3b;
+        const T p36AC = T(36) * pAC;
         if (it < S) {  // phi^- at node i: weights (1/10, 6/10, 3/10) on (A, B, C)
             const T q1 = c + (e2 + T(2) * e3) * T(1.0 / 6.0);
-            const T num = pBC * (D3a * T(1.0 / 3.0)) + pAB * (D3b * T(0.5));
-            um[it] = q1 + wdiv(num, pBC + p6AC + T(3) * pAB);
+            const T num = (xa + xa) + T(3) * xb;                // 6 (pBC D3a/3 + pAB D3b/2)
+            um[it] = q1 + wdiv(num, (T(6) * pBC + p36AC) + T(18) * pAB);
         }
         if (it > 0) {  // phi^+ at node i-1: the mirrored sub-stencils, (1/10, 6/10, 3/10) on (C, B, A)
             const T qp1 = c - (e3 + T(2) * e2) * T(1.0 / 6.0);
-            const T num = pAB * (D3b * T(1.0 / 3.0)) + pBC * (D3a * T(0.5));
-            up[it - 1] = qp1 - wdiv(num, pAB + p6AC + T(3) * pBC);
+            const T num = (xb + xb) + T(3) * xa;                // 6 (pAB D3b/3 + pBC D3a/2)
+            up[it - 1] = qp1 - wdiv(num, (T(6) * pAB + p36AC) + T(18) * pBC);
         }
         e1 = e2;
         e2 = e3;
