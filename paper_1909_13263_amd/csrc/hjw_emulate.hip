@@ -139,15 +139,21 @@ struct Emu {
             }
             // the row threads and the column threads, then the barrier, then the finish
             std::vector<T> vm(size_t(TL::kHalf) * kSY), vp(size_t(TL::kHalf) * kSY);
+            std::vector<T> vL(TL::kVElems, T(NAN));
             for (int t = 0; t < TL::kHalf; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
-            for (int t = 0; t < TL::kHalf; ++t)
+            for (int t = 0; t < TL::kHalf; ++t) {
                 TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY]);
+                TL::stash(t, &vm[size_t(t) * kSY], &vp[size_t(t) * kSY], vL.data());
+            }
             double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY;
             bool bad = false;
-            for (int t = 0; t < TL::kHalf; ++t) {
+            for (int t = 0; t < TL::kThreads; ++t) {
+                // row threads (t < kHalf) finish from the stash, column threads from registers
+                const bool col_half = t >= TL::kHalf;
+                const int u = col_half ? t - TL::kHalf : t;
                 Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
-                TL::finish(t, uL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY], phiL.data(),
-                           kCenter ? pnL.data() : nullptr, fin);
+                TL::finish(u, col_half, uL.data(), &vm[size_t(u) * kSY], &vp[size_t(u) * kSY],
+                           vL.data(), phiL.data(), kCenter ? pnL.data() : nullptr, fin);
                 lu = std::fmin(lu, double(fin.lo_u));
                 hu = std::fmax(hu, double(fin.hi_u));
                 lv = std::fmin(lv, double(fin.lo_v));

@@ -192,6 +192,7 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
     __shared__ P pnL[kCenter ? TL::kCenterElems : 1];
+    __shared__ T vL[TL::kVElems];
     const int nb = a.nbx * a.nby;
     const int tile = tile_of_block(bid, nb, a.remap);
     const int64_t x0 = int64_t(tile % a.nbx) * kTX;
@@ -211,13 +212,16 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     __syncthreads();
     T vm[kSY], vp[kSY];
     const bool rows = tid < TL::kHalf;   // wave-uniform: the first half of the waves march rows
-    if (rows)
+    if (rows) {
         TL::sweep_x(tid, a, phiL, uL);
-    else
+    } else {
         TL::sweep_y(tid - TL::kHalf, a, phiL, vm, vp);
+        TL::stash(tid - TL::kHalf, vm, vp, vL);
+    }
     __syncthreads();
     Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
-    if (!rows) TL::finish(tid - TL::kHalf, uL, vm, vp, phiL, kCenter ? pnL : nullptr, fin);
+    TL::finish(rows ? tid : tid - TL::kHalf, !rows, uL, vm, vp, vL, phiL,
+               kCenter ? pnL : nullptr, fin);
 
     if (STAGE == kStagePre) {
         fold_range<TL::kThreads / 64>(a, bid, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad);

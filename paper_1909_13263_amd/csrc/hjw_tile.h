@@ -615,17 +615,38 @@ struct Tile {
         sweep<T, P, SY>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy, vm, vp);
     }
 
-    // After the barrier: fin(col, row, um, up, vm, vp, phi_s, phi^n) for the thread's SY
-    // nodes, with the stage input and phi^n of the node taken from LDS.
-    template <class Fin>
-    __host__ __device__ static void finish(int t, const T* uL, const T* vm, const T* vp,
-                                           const P* phiL, const P* pnL, Fin& fin) {
+    // The finish is shared by all threads: a column thread keeps the first SY/2 of its
+    // nodes and, before the barrier, stashes phi_y^-+ of the other SY/2 in vL, where
+    // the row thread of the same index picks them up.
+    static constexpr int kKeep = SY / 2;
+    static constexpr int kVElems = 2 * TY * TX / 2;
+    __host__ __device__ static void stash(int t, const T* vm, const T* vp, T* vL) {
         const int col = t % TX;
         const int seg = t / TX;
 #pragma unroll
-        for (int k = 0; k < SY; ++k) {
-            const int row = seg * SY + k;
-            fin(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col], vm[k], vp[k],
+        for (int k = kKeep; k < SY; ++k) {
+            const int slot = (seg * kKeep + (k - kKeep)) * TX + col;
+            vL[slot] = vm[k];
+            vL[kVElems / 2 + slot] = vp[k];
+        }
+    }
+
+    // After the barrier: fin(col, row, um, up, vm, vp, phi_s, phi^n) for SY/2 nodes of
+    // column t % TX, with the stage input and phi^n of the node taken from LDS.  Column
+    // threads (col_half) pass their registers; row threads read the stash.
+    template <class Fin>
+    __host__ __device__ static void finish(int t, bool col_half, const T* uL, const T* vm,
+                                           const T* vp, const T* vL, const P* phiL,
+                                           const P* pnL, Fin& fin) {
+        const int col = t % TX;
+        const int seg = t / TX;
+#pragma unroll
+        for (int j = 0; j < kKeep; ++j) {
+            const int row = seg * SY + (col_half ? j : kKeep + j);
+            const int slot = (seg * kKeep + j) * TX + col;
+            const T m = col_half ? vm[j] : vL[slot];
+            const T p = col_half ? vp[j] : vL[kVElems / 2 + slot];
+            fin(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col], m, p,
                 phiL[(row + 3) * PW + col + 3], pnL ? pnL[row * TX + col] : P(0));
         }
     }
