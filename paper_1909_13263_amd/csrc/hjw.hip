@@ -158,9 +158,11 @@ template <typename T, typename P, int STAGE>
 hipError_t launch_stage(const hjw_grid* g, StageArgs<T, P> a) {
     const dim3 grid(unsigned(g->nbx * g->nby));
     if (g->dim == 2 && g->tile_rows == 32)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32>), grid, dim3(512), 0, g->stream, a);
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32>), grid, dim3(threads2d(32)), 0, g->stream,
+                           a);
     else if (g->dim == 2)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16>), grid, dim3(256), 0, g->stream, a);
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16>), grid, dim3(threads2d(16)), 0, g->stream,
+                           a);
     else
         hipLaunchKernelGGL((k_stage1d<T, P, STAGE>), grid, dim3(256), 0, g->stream, a);
     return hipGetLastError();

@@ -11,12 +11,6 @@
 
 namespace hjw {
 
-// Tile shapes: 64 x TY nodes per workgroup in 2-D (segments of 8 per thread;
-// TY = 16 with 256 threads or TY = 32 with 512 threads), 1024 nodes in 1-D
-// (segments of 4).
-constexpr int kTX = 64, kSX = 8, kSY = 8;
-constexpr int kTX1 = 1024, kS1 = 4;
-
 // Thread-local text of the last error (defined in hjw.hip).
 std::string& last_error();
 

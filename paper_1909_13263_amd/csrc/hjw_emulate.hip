@@ -21,9 +21,7 @@ using namespace hjw;
 
 namespace {
 
-constexpr int kTX = 64, kSX = 8, kSY = 8;
 int g_tile_rows = 32;  // 2-D tile height being emulated (32 or 16)
-constexpr int kTX1 = 1024, kS1 = 4;
 constexpr size_t kGuard = 4096;
 
 template <typename X>

@@ -182,12 +182,11 @@ __device__ inline bool stage_entry(const StageArgs<T, P>& a, int bid, double& dt
 }
 
 // One workgroup's share of a stage on a 2-D grid: bid is the workgroup's index among
-// the grid's nbx * nby tiles.  2 (TX / SX) TY threads: row threads and column threads
-// (16 TY for 64-wide tiles).
+// the grid's nbx * nby tiles; threads2d(TY) threads, half row and half column threads.
 template <typename T, typename P, int STAGE, int TY>
 __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     using TL = Tile<T, P, kTX, TY, kSX, kSY>;
-    static_assert(TL::kThreads == 16 * TY, "launch bounds");
+    static_assert(TL::kThreads == threads2d(TY), "launch bounds");
     constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
@@ -231,7 +230,7 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
 }
 
 template <typename T, typename P, int STAGE, int TY>
-__global__ __launch_bounds__(16 * TY) void k_stage2d(StageArgs<T, P> a) {
+__global__ __launch_bounds__(threads2d(TY)) void k_stage2d(StageArgs<T, P> a) {
     stage_tile2d<T, P, STAGE, TY>(a, int(blockIdx.x));
 }
 

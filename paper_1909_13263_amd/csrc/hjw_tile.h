@@ -56,6 +56,15 @@ constexpr int kStageDeriv = 3;  // derivatives only (u-, u+, v-, v+ as FP64)
 
 constexpr double kEps = 1.0e-6;  // epsilon of eq. (WLOC1)
 
+// Tile shapes: 64 x TY nodes per workgroup in 2-D, each thread marching a segment
+// of kSX nodes along a row and then finishing kSY/2 nodes (TY = 16 or 32); 1024
+// nodes in 1-D (segments of 4).
+constexpr int kTX = 64, kSX = 8, kSY = 8;
+constexpr int kTX1 = 1024, kS1 = 4;
+static_assert(kSX == kSY, "row and column threads pair up one to one");
+// Threads of a 2-D workgroup: as many row threads as column threads.
+constexpr int threads2d(int ty) { return 2 * (kTX / kSX) * ty; }
+
 // Step state kept on the device so that whole steps can be replayed from a graph.
 struct DevState {
     double t;
