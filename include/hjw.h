@@ -67,8 +67,12 @@ typedef enum {
     HJW_OPT_KERNEL_EVENTS = 1, /* 1: launch eagerly and bracket every kernel of a step with
                                   HIP events on the grid's stream; resets the totals that
                                   hjw_kernel_times reports.  0 (default): off. */
-    HJW_OPT_TILE_ROWS = 2      /* 2-D tile height: 16 (default: 64 x 16 nodes, 256 threads)
-                                  or 32 (64 x 32 nodes, 512 threads).  Results are identical. */
+    HJW_OPT_TILE_ROWS = 2,     /* 2-D tile height: 16 (default: 64 x 16 nodes) or 32 (64 x 32
+                                  nodes, 8-node segments only).  Results are identical. */
+    HJW_OPT_SEGMENT = 3        /* nodes each thread marches in the 2-D sweeps: 0 (default)
+                                  automatic, 4 (FP32 stencil, 16-row tiles: 512 threads per
+                                  tile) or 8 (256 threads per 16-row tile).  Results are
+                                  identical. */
 } hjw_option;
 
 typedef struct hjw_grid hjw_grid;

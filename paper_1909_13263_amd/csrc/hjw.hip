@@ -22,6 +22,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "hjw.h"
@@ -69,6 +70,7 @@ struct hjw_grid {
     int par = 0;
     int nbx = 0, nby = 0;
     int tile_rows = 16;  // 2-D tile height (16 or 32)
+    int seg_opt = 0;     // nodes per thread in the 2-D sweeps: 0 automatic, 4 or 8
 
     // host mirror
     DevState* pinned = nullptr;  // pinned host copy of the device state
@@ -154,15 +156,30 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     return a;
 }
 
+// Segment length of the 2-D sweeps: 4 nodes per thread (twice the waves) for the
+// FP32 stencil on 16-row tiles when the grid has at most 8 tiles per compute unit, so
+// that small grids still keep every SIMD busy; 8 otherwise (fewer instructions per
+// node).  FP64 keeps 8: its registers leave no room for the extra waves.
+constexpr int kSmallGridTiles = 2048;
+int segment(const hjw_grid* g) {
+    if (g->seg_opt) return g->seg_opt;
+    return (g->prec != HJW_FP64 && g->tile_rows == 16 && g->nbx * g->nby <= kSmallGridTiles) ? 4
+                                                                                          : 8;
+}
+
 template <typename T, typename P, int STAGE>
 hipError_t launch_stage(const hjw_grid* g, StageArgs<T, P> a) {
     const dim3 grid(unsigned(g->nbx * g->nby));
+    constexpr bool kNarrow = !std::is_same<T, double>::value;   // the S = 4 kernels
     if (g->dim == 2 && g->tile_rows == 32)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32>), grid, dim3(threads2d(32)), 0, g->stream,
-                           a);
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32, 8>), grid, dim3(threads2d(32, 8)), 0,
+                           g->stream, a);
+    else if (g->dim == 2 && kNarrow && segment(g) == 4)
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, kNarrow ? 4 : 8>), grid,
+                           dim3(threads2d(16, 4)), 0, g->stream, a);
     else if (g->dim == 2)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16>), grid, dim3(threads2d(16)), 0, g->stream,
-                           a);
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, 8>), grid, dim3(threads2d(16, 8)), 0,
+                           g->stream, a);
     else
         hipLaunchKernelGGL((k_stage1d<T, P, STAGE>), grid, dim3(256), 0, g->stream, a);
     return hipGetLastError();
@@ -545,8 +562,19 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
         if (!g->use_graph) drop_graph(g);
         return HJW_OK;
     }
+    if (option == HJW_OPT_SEGMENT) {
+        if (value != 0 && value != 4 && value != 8)
+            return fail(HJW_EINVAL, "segment must be 0 (automatic), 4 or 8");
+        if (value == 4 && (g->prec == HJW_FP64 || g->tile_rows != 16))
+            return fail(HJW_EINVAL, "4-node segments need 16-row tiles and an FP32 stencil");
+        g->seg_opt = int(value);
+        drop_graph(g);
+        return HJW_OK;
+    }
     if (option == HJW_OPT_TILE_ROWS) {
         if (value != 16 && value != 32) return fail(HJW_EINVAL, "tile rows must be 16 or 32");
+        if (value == 32 && g->seg_opt == 4)
+            return fail(HJW_EINVAL, "32-row tiles take 8-node segments");
         g->tile_rows = int(value);
         if (g->dim == 2) g->nby = int((g->ny + g->tile_rows - 1) / g->tile_rows);
         drop_graph(g);

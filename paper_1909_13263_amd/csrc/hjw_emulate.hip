@@ -22,6 +22,7 @@ using namespace hjw;
 namespace {
 
 int g_tile_rows = 32;  // 2-D tile height being emulated (32 or 16)
+int g_segment = 8;     // nodes per thread in the 2-D sweeps (8, or 4 with 16-row tiles)
 constexpr size_t kGuard = 4096;
 
 template <typename X>
@@ -104,17 +105,19 @@ struct Emu {
     // Run one stage over all tiles, the way the kernel does.
     template <int STAGE>
     void stage(StageArgs<T, P> a, double dt, double ax, double ay) {
-        if (pr.dim == 2 && g_tile_rows == 16)
-            stage2d<STAGE, 16>(a, dt, ax, ay);
+        if (pr.dim == 2 && g_tile_rows == 16 && g_segment == 4)
+            stage2d<STAGE, 16, 4>(a, dt, ax, ay);
+        else if (pr.dim == 2 && g_tile_rows == 16)
+            stage2d<STAGE, 16, 8>(a, dt, ax, ay);
         else if (pr.dim == 2)
-            stage2d<STAGE, 32>(a, dt, ax, ay);
+            stage2d<STAGE, 32, 8>(a, dt, ax, ay);
         else
             stage1d<STAGE>(a, dt, ax, ay);
     }
 
-    template <int STAGE, int TY>
+    template <int STAGE, int TY, int S>
     void stage2d(StageArgs<T, P> a, double dt, double ax, double ay) {
-        using TL = Tile<T, P, kTX, TY, kSX, kSY>;
+        using TL = Tile<T, P, kTX, TY, S, S>;
         const int nb = nbx * nby;
         std::vector<P> phiL(TL::kPhiElems), pnL(TL::kCenterElems);
         std::vector<T> uL(TL::kUElems);
@@ -136,12 +139,12 @@ struct Emu {
                     TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data(), pnL.data());
             }
             // the row threads and the column threads, then the barrier, then the finish
-            std::vector<T> vm(size_t(TL::kHalf) * kSY), vp(size_t(TL::kHalf) * kSY);
+            std::vector<T> vm(size_t(TL::kHalf) * S), vp(size_t(TL::kHalf) * S);
             std::vector<T> vL(TL::kVElems, T(NAN));
             for (int t = 0; t < TL::kHalf; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
             for (int t = 0; t < TL::kHalf; ++t) {
-                TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * kSY], &vp[size_t(t) * kSY]);
-                TL::stash(t, &vm[size_t(t) * kSY], &vp[size_t(t) * kSY], vL.data());
+                TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * S], &vp[size_t(t) * S]);
+                TL::stash(t, &vm[size_t(t) * S], &vp[size_t(t) * S], vL.data());
             }
             double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY;
             bool bad = false;
@@ -150,7 +153,7 @@ struct Emu {
                 const bool col_half = t >= TL::kHalf;
                 const int u = col_half ? t - TL::kHalf : t;
                 Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
-                TL::finish(u, col_half, uL.data(), &vm[size_t(u) * kSY], &vp[size_t(u) * kSY],
+                TL::finish(u, col_half, uL.data(), &vm[size_t(u) * S], &vp[size_t(u) * S],
                            vL.data(), phiL.data(), kCenter ? pnL.data() : nullptr, fin);
                 lu = std::fmin(lu, double(fin.lo_u));
                 hu = std::fmax(hu, double(fin.hi_u));
@@ -280,7 +283,17 @@ extern "C" {
 // Height of the emulated 2-D tile (32 or 16), as HJW_OPT_TILE_ROWS selects on the GPU.
 int hjw_emu_set_tile_rows(int rows) {
     if (rows != 16 && rows != 32) return -1;
+    if (rows == 32 && g_segment != 8) return -1;
     g_tile_rows = rows;
+    return 0;
+}
+
+// Nodes per thread in the emulated 2-D sweeps (8, or 4 with 16-row tiles), as
+// HJW_OPT_SEGMENT selects on the GPU.
+int hjw_emu_set_segment(int seg) {
+    if (seg != 4 && seg != 8) return -1;
+    if (seg == 4 && g_tile_rows != 16) return -1;
+    g_segment = seg;
     return 0;
 }
 

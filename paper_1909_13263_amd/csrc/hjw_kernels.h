@@ -182,11 +182,12 @@ __device__ inline bool stage_entry(const StageArgs<T, P>& a, int bid, double& dt
 }
 
 // One workgroup's share of a stage on a 2-D grid: bid is the workgroup's index among
-// the grid's nbx * nby tiles; threads2d(TY) threads, half row and half column threads.
-template <typename T, typename P, int STAGE, int TY>
+// the grid's nbx * nby tiles; threads2d(TY, S) threads, half row and half column
+// threads, each marching S nodes.
+template <typename T, typename P, int STAGE, int TY, int S>
 __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
-    using TL = Tile<T, P, kTX, TY, kSX, kSY>;
-    static_assert(TL::kThreads == threads2d(TY), "launch bounds");
+    using TL = Tile<T, P, kTX, TY, S, S>;
+    static_assert(TL::kThreads == threads2d(TY, S), "launch bounds");
     constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
     __shared__ P phiL[TL::kPhiElems];
     __shared__ T uL[TL::kUElems];
@@ -209,7 +210,7 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
         TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
     }
     __syncthreads();
-    T vm[kSY], vp[kSY];
+    T vm[S], vp[S];
     const bool rows = tid < TL::kHalf;   // wave-uniform: the first half of the waves march rows
     if (rows) {
         TL::sweep_x(tid, a, phiL, uL);
@@ -229,9 +230,9 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     }
 }
 
-template <typename T, typename P, int STAGE, int TY>
-__global__ __launch_bounds__(threads2d(TY)) void k_stage2d(StageArgs<T, P> a) {
-    stage_tile2d<T, P, STAGE, TY>(a, int(blockIdx.x));
+template <typename T, typename P, int STAGE, int TY, int S>
+__global__ __launch_bounds__(threads2d(TY, S)) void k_stage2d(StageArgs<T, P> a) {
+    stage_tile2d<T, P, STAGE, TY, S>(a, int(blockIdx.x));
 }
 
 template <typename T, typename P, int STAGE>

@@ -33,7 +33,7 @@ namespace hjw {
 // arguments with the parity it has when flip is 0; tile_start[g] is its first tile
 // (tile_start[ngrids] = total tiles).  Workgroups past the last tile exit.
 template <typename T, typename P, int STAGE>
-__global__ __launch_bounds__(threads2d(16)) void k_stage2d_batch(const StageArgs<T, P>* table,
+__global__ __launch_bounds__(threads2d(16, 8)) void k_stage2d_batch(const StageArgs<T, P>* table,
                                                       const int* tile_start, const int* ngrids,
                                                       int flip) {
     const int ng = *ngrids;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(threads2d(16)) void k_stage2d_batch(const StageArgs
     // the second stage writes phi_2, the third phi^{n+1} over phi^n
     if (STAGE == kStageMid) a.out = const_cast<P*>(a.phi_s);
     if (STAGE == kStageLast) a.out = const_cast<P*>(a.phi_n);
-    stage_tile2d<T, P, STAGE, 16>(a, b - tile_start[lo]);
+    stage_tile2d<T, P, STAGE, 16, 8>(a, b - tile_start[lo]);
 }
 
 // A newly admitted solve: record 0 is current (t = 0, target t_final), slots empty.
@@ -304,7 +304,7 @@ void write_table(hjw_server* s) {
 template <typename T, typename P>
 hipError_t launch_batched_step(hjw_server* s, int flip) {
     const StageArgs<T, P>* tab = static_cast<const StageArgs<T, P>*>(s->d_table);
-    const dim3 grid(unsigned(std::max(1, s->launch_tiles))), block(threads2d(kTY));
+    const dim3 grid(unsigned(std::max(1, s->launch_tiles))), block(threads2d(kTY, 8));
     hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre>), grid, block, 0, s->stream, tab,
                        s->d_tile_start, s->d_ngrids, flip);
     hipError_t e = hipGetLastError();

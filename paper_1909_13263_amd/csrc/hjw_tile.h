@@ -56,14 +56,14 @@ constexpr int kStageDeriv = 3;  // derivatives only (u-, u+, v-, v+ as FP64)
 
 constexpr double kEps = 1.0e-6;  // epsilon of eq. (WLOC1)
 
-// Tile shapes: 64 x TY nodes per workgroup in 2-D, each thread marching a segment
-// of kSX nodes along a row and then finishing kSY/2 nodes (TY = 16 or 32); 1024
-// nodes in 1-D (segments of 4).
-constexpr int kTX = 64, kSX = 8, kSY = 8;
+// Tile shapes: 64 x TY nodes per workgroup in 2-D (TY = 16 or 32), each thread
+// marching a segment of S nodes along a row or a column (S = 8, or S = 4 for twice
+// the threads on grids too small to fill the GPU) and then finishing S/2 nodes;
+// 1024 nodes in 1-D (segments of 4).
+constexpr int kTX = 64;
 constexpr int kTX1 = 1024, kS1 = 4;
-static_assert(kSX == kSY, "row and column threads pair up one to one");
 // Threads of a 2-D workgroup: as many row threads as column threads.
-constexpr int threads2d(int ty) { return 2 * (kTX / kSX) * ty; }
+constexpr int threads2d(int ty, int seg) { return 2 * (kTX / seg) * ty; }
 
 // Step state kept on the device so that whole steps can be replayed from a graph.
 struct DevState {
@@ -108,10 +108,15 @@ __device__ inline bool any_lane(bool p) { return __any(p ? 1 : 0) != 0; }
 __host__ inline bool any_lane(bool p) { return p; }
 // Products that are rounded on their own (never fused into an add), so that sums
 // like a*u + b*v are symmetric under exchanging (a,u) and (b,v) bit for bit.
-__device__ inline float mul_rn(float a, float b) { return __fmul_rn(a, b); }
-__host__ inline float mul_rn(float a, float b) { return a * b; }
-__device__ inline double mul_rn(double a, double b) { return __dmul_rn(a, b); }
-__host__ inline double mul_rn(double a, double b) { return a * b; }
+// (The pragma takes the product out of FMA contraction; __fmul_rn does not.)
+__host__ __device__ inline float mul_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__host__ __device__ inline double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
 
 template <typename T>
 __host__ __device__ inline bool finite_t(T x) {
@@ -253,10 +258,12 @@ __host__ __device__ inline void weight_products(float MA, float MB, float MC, fl
 template <typename T, typename P, int S>
 __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T eps4, T* um,
                                       T* up) {
+    // The quotients are rounded on their own: fused into the differences that follow,
+    // they would round differently at the ends of a segment than inside it.
     T v[S + 5];
 #pragma unroll
     for (int k = 0; k < S + 5; ++k)
-        v[k] = T((line[(k + 1) * stride] - line[k * stride]) * ihP);
+        v[k] = T(mul_rn(line[(k + 1) * stride] - line[k * stride], ihP));
     T e1 = v[1] - v[0], e2 = v[2] - v[1], e3 = v[3] - v[2];
     T c0 = e2 * ih;
 #pragma unroll

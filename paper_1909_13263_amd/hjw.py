@@ -22,6 +22,7 @@ H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM = 0, 1, 2, 3
 OPT_USE_GRAPH = 0
 OPT_KERNEL_EVENTS = 1
 OPT_TILE_ROWS = 2
+OPT_SEGMENT = 3
 KERNEL_NAMES = ("pre", "finalize", "mid", "last")
 
 PREC_NAMES = {"fp64": FP64, "fp32_mixed": FP32_MIXED, "fp32": FP32}

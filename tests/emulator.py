@@ -23,6 +23,8 @@ def lib():
                                           ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp]
         L.hjw_emu_set_tile_rows.restype = ctypes.c_int
         L.hjw_emu_set_tile_rows.argtypes = [ctypes.c_int]
+        L.hjw_emu_set_segment.restype = ctypes.c_int
+        L.hjw_emu_set_segment.argtypes = [ctypes.c_int]
         L.hjw_emu_step.restype = ctypes.c_int
         L.hjw_emu_step.argtypes = [ctypes.c_int, i64, i64, d, d, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, vp, vp, d, d, d, vp]
@@ -32,6 +34,14 @@ def lib():
 
 def set_tile_rows(rows):
     assert lib().hjw_emu_set_tile_rows(int(rows)) == 0
+
+
+def set_tile(rows, segment):
+    """2-D tile height and nodes per thread of the emulated kernels."""
+    L = lib()
+    assert L.hjw_emu_set_segment(8) == 0
+    assert L.hjw_emu_set_tile_rows(int(rows)) == 0
+    assert L.hjw_emu_set_segment(int(segment)) == 0
 
 
 def _p(a):

@@ -79,6 +79,24 @@ def test_calls_on_unbound_grid_fail_cleanly():
     L.hjw_grid_destroy(None)
 
 
+def test_segment_and_tile_options_are_validated():
+    """Host-side checks of HJW_OPT_SEGMENT / HJW_OPT_TILE_ROWS on a grid with no workspace."""
+    L = hjw.lib()
+    rc, h64 = _create(2, [256, 256], [0, 0], [1, 1], [0, 0], hjw.FP64)
+    rc2, h32 = _create(2, [256, 256], [0, 0], [1, 1], [0, 0], hjw.FP32_MIXED)
+    assert rc == 0 and rc2 == 0
+    assert L.hjw_set_option(h64, hjw.OPT_SEGMENT, 4) == hjw.EINVAL     # FP64 keeps 8
+    assert L.hjw_set_option(h64, hjw.OPT_SEGMENT, 8) == hjw.OK
+    assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 5) == hjw.EINVAL
+    assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 4) == hjw.OK
+    assert L.hjw_set_option(h32, hjw.OPT_TILE_ROWS, 32) == hjw.EINVAL  # 32 rows take 8
+    assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 0) == hjw.OK
+    assert L.hjw_set_option(h32, hjw.OPT_TILE_ROWS, 32) == hjw.OK
+    assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 4) == hjw.EINVAL
+    L.hjw_grid_destroy(h64)
+    L.hjw_grid_destroy(h32)
+
+
 def test_header_declares_the_server():
     names = _declared()
     for required in ["hjw_server_footprint", "hjw_server_create", "hjw_server_submit",

@@ -20,11 +20,11 @@ SHAPES = [(8,), (37,), (160,), (1030,), (8, 8), (33, 65), (40, 70), (64, 64), (9
           (100, 200), (135, 260)]
 
 
-@pytest.fixture(params=[32, 16], ids=["tile64x32", "tile64x16"])
+@pytest.fixture(params=[(32, 8), (16, 8), (16, 4)], ids=["tile64x32", "tile64x16", "tile64x16s4"])
 def tile_rows(request):
-    EM.set_tile_rows(request.param)
+    EM.set_tile(*request.param)
     yield request.param
-    EM.set_tile_rows(32)
+    EM.set_tile(32, 8)
 
 
 @pytest.mark.parametrize("shape", SHAPES)
