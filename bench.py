@@ -50,9 +50,16 @@ def kernel_bytes_per_cell(phi_b, flux_b):
 # counters: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
 # counters read for a plain 256 MiB copy kernel.  Valid only for the kernel sources whose
 # SHA-256 is recorded; any change to them turns the figure into null until re-measured.
-MEASURED_TRAFFIC = {"source_sha256": "5b2bf539aba67f33fbf0218a5dae1bde9a4ff0fb8795a5632e361ba70497064b",
+MEASURED_TRAFFIC = {"source_sha256": "efa3f91638519505ee61db7077270350f3788d9621004c52cd9f0b72031f1b43",
                     "n": 1024, "tile_rows": 16,
-                    "bytes": {"pre": 22138394, "mid": 31241380, "last": 26292146}}
+                    "bytes": {"pre": 21787504, "mid": 30773320, "last": 25829632}}
+
+
+def segment(n):
+    """Nodes per thread the library picks for the FP32 stencil on an n x n grid (4 on
+    grids of at most 2048 tiles of 64 x 16, else 8)."""
+    tiles = -(-n // 64) * -(-n // 16)
+    return 4 if tiles <= 2048 else 8
 
 
 def kernel_source_sha():
@@ -294,7 +301,7 @@ def main():
                                "t=0.5/pi^2",
                    "cells": cells, "rk_steps": main_res["rk_steps"],
                    "stages_per_solve": main_res["stages"]},
-        "roofline": {"bound": "alu", "kernel": f"k_stage2d<float,double,{dom}>",
+        "roofline": {"bound": "alu", "kernel": f"k_stage2d<float,double,{dom},16,{segment(args.n)}>",
                      "achieved": alu_achieved, "peak": VALU_PEAK_GSLOTS,
                      "unit": "G lane-slots/s", "frac": alu_achieved / VALU_PEAK_GSLOTS,
                      "traffic": traffic, "avg_launch_ms": dom_ms,
