@@ -20,6 +20,7 @@
 #include <limits>
 #include <map>
 #include <new>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -31,13 +32,16 @@ namespace hjw {
 
 // One batched launch of a stage over all admitted solves.  table[g] holds solve g's
 // arguments with the parity it has when flip is 0; tile_start[g] is its first tile
-// (tile_start[ngrids] = total tiles).  Workgroups past the last tile exit.
-template <typename T, typename P, int STAGE>
-__global__ __launch_bounds__(threads2d(16, 8)) void k_stage2d_batch(const StageArgs<T, P>* table,
-                                                      const int* tile_start, const int* ngrids,
-                                                      int flip) {
+// (tile_start[ngrids] = total tiles).  Workgroups past the last tile exit.  The launch
+// size is a multiple of 8: workgroup w goes to tile (w % 8) * (size / 8) + w / 8, so that
+// each XCD (dealt workgroups round-robin) works through one contiguous run of tiles and
+// their shared halos stay in its L2.
+template <typename T, typename P, int STAGE, int S>
+__global__ __launch_bounds__(threads2d(16, S)) void k_stage2d_batch(const StageArgs<T, P>* table,
+                                                                   const int* tile_start,
+                                                                   const int* ngrids, int flip) {
     const int ng = *ngrids;
-    const int b = int(blockIdx.x);
+    const int b = int(blockIdx.x % 8u * (gridDim.x / 8u) + blockIdx.x / 8u);
     if (ng <= 0 || b >= tile_start[ng]) return;
     int lo = 0, hi = ng;  // tile_start[lo] <= b < tile_start[hi]
     while (hi - lo > 1) {
@@ -52,7 +56,7 @@ __global__ __launch_bounds__(threads2d(16, 8)) void k_stage2d_batch(const StageA
     // the second stage writes phi_2, the third phi^{n+1} over phi^n
     if (STAGE == kStageMid) a.out = const_cast<P*>(a.phi_s);
     if (STAGE == kStageLast) a.out = const_cast<P*>(a.phi_n);
-    stage_tile2d<T, P, STAGE, 16, 8>(a, b - tile_start[lo]);
+    stage_tile2d<T, P, STAGE, 16, S>(a, b - tile_start[lo]);
 }
 
 // A newly admitted solve: record 0 is current (t = 0, target t_final), slots empty.
@@ -301,21 +305,32 @@ void write_table(hjw_server* s) {
     s->launch_tiles = launch_size(tiles);
 }
 
-template <typename T, typename P>
-hipError_t launch_batched_step(hjw_server* s, int flip) {
+template <typename T, typename P, int S>
+hipError_t launch_batched_step_s(hjw_server* s, int flip) {
     const StageArgs<T, P>* tab = static_cast<const StageArgs<T, P>*>(s->d_table);
-    const dim3 grid(unsigned(std::max(1, s->launch_tiles))), block(threads2d(kTY, 8));
-    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre>), grid, block, 0, s->stream, tab,
+    const dim3 grid(unsigned(s->launch_tiles)), block(threads2d(kTY, S));
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre, S>), grid, block, 0, s->stream, tab,
                        s->d_tile_start, s->d_ngrids, flip);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageMid>), grid, block, 0, s->stream, tab,
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageMid, S>), grid, block, 0, s->stream, tab,
                        s->d_tile_start, s->d_ngrids, flip);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageLast>), grid, block, 0, s->stream, tab,
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageLast, S>), grid, block, 0, s->stream, tab,
                        s->d_tile_start, s->d_ngrids, flip);
     return hipGetLastError();
+}
+
+// Launches of at most kSmallLaunch tiles use 4-node segments with the FP32 stencil (twice
+// the waves), as a single grid of that size would; both give the same bits.
+constexpr int kSmallLaunch = 2048;
+
+template <typename T, typename P>
+hipError_t launch_batched_step(hjw_server* s, int flip) {
+    if (!std::is_same<T, double>::value && s->launch_tiles <= kSmallLaunch)
+        return launch_batched_step_s<T, P, std::is_same<T, double>::value ? 8 : 4>(s, flip);
+    return launch_batched_step_s<T, P, 8>(s, flip);
 }
 
 hipError_t batched_step(hjw_server* s, int flip) {
