@@ -165,7 +165,7 @@ def accuracy_cases():
         ("burgers2d 1024^2 t=1.5/pi^2", W.burgers2d(1024, 1.5 / math.pi**2),
          (hjw.FP32_MIXED, hjw.FP32)),
         ("negcos2d 2048^2 t=1.0", W.negcos2d(2048, 1.0), (hjw.FP32_MIXED,)),
-        ("levelset2d 4096^2 t=0.2", W.levelset2d(4096, 0.2), (hjw.FP32,)),
+        ("levelset2d 4096^2 t=0.2", W.levelset2d(4096, 0.2), (hjw.FP32_MIXED, hjw.FP32)),
     ]
 
 

@@ -1,0 +1,65 @@
+"""FP32 error bounds of the full-size configurations, whole solves on the GPU.
+
+Each configuration is solved to its final time in FP64 and in the FP32 path(s) it is
+quoted with.  The FP64 GPU path matches the FP64 oracle to 1e-12 of max|phi| (whole
+solves at reduced size and a few whole steps at these sizes in test_gpu_parity.py);
+solving these sizes to the final time on the CPU oracle would take hours, so the FP64
+GPU result stands in for it here.  L1 is the grid mean of |error|.
+
+Bounds (about 2-4x the measured errors):
+  Burgers 1024^2, t = 0.5/pi^2   stencil L-inf 1e-7,  L1 2e-8;  storage L-inf 5e-6, L1 1e-6
+  Burgers 1024^2, t = 1.5/pi^2   stencil L-inf 2e-7,  L1 2e-8;  storage L-inf 2e-5, L1 3e-6
+  -cos 2048^2,    t = 1.0        stencil L-inf 1.5e-7, L1 6e-8
+  level set 4096^2, t = 0.2      stencil L-inf 1e-3,  L1 2e-6;  storage L-inf 1e-3, L1 1e-5
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1909_13263_amd import hjw
+from paper_1909_13263_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED, FP32 = hjw.FP64, hjw.FP32_MIXED, hjw.FP32
+
+CASES = [
+    ("burgers-smooth", lambda: W.burgers2d(1024, 0.5 / math.pi**2),
+     {MIXED: (1e-7, 2e-8), FP32: (5e-6, 1e-6)}),
+    ("burgers-kinks", lambda: W.burgers2d(1024, 1.5 / math.pi**2),
+     {MIXED: (2e-7, 2e-8), FP32: (2e-5, 3e-6)}),
+    ("negcos-2048", lambda: W.negcos2d(2048, 1.0), {MIXED: (1.5e-7, 6e-8)}),
+    ("levelset-4096", lambda: W.levelset2d(4096, 0.2), {MIXED: (1e-3, 2e-6), FP32: (1e-3, 1e-5)}),
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    yield
+
+
+def _solve(pr, prec):
+    g = hjw.grid_for(pr, prec)
+    g.set_phi(pr.phi0())
+    info = g.step_to(pr.t_final, pr.cfl)
+    phi = g.get_phi()
+    g.close()
+    assert info.t == pr.t_final
+    return phi, info
+
+
+@pytest.mark.parametrize("name,make,bounds", CASES, ids=[c[0] for c in CASES])
+def test_fp32_error_bounds_at_full_size(name, make, bounds):
+    pr = make()
+    ref, info = _solve(pr, FP64)
+    assert np.isfinite(ref).all()
+    for prec, (linf_max, l1_max) in bounds.items():
+        phi, pinfo = _solve(pr, prec)
+        err = np.abs(phi - ref)
+        linf, l1 = float(err.max()), float(err.mean())
+        print(f"{name} prec={prec} steps={pinfo.steps}/{info.steps} linf={linf:.3e} l1={l1:.3e}")
+        assert abs(pinfo.steps - info.steps) <= 1
+        assert linf <= linf_max and l1 <= l1_max
