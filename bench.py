@@ -57,9 +57,9 @@ MEASURED_TRAFFIC = {"source_sha256": "efa3f91638519505ee61db7077270350f3788d9621
 
 def segment(n):
     """Nodes per thread the library picks for the FP32 stencil on an n x n grid (4 on
-    grids of at most 2048 tiles of 64 x 16, else 8)."""
+    grids of at most 640 tiles of 64 x 16, else 8)."""
     tiles = -(-n // 64) * -(-n // 16)
-    return 4 if tiles <= 2048 else 8
+    return 4 if tiles <= 640 else 8
 
 
 def kernel_source_sha():

@@ -157,10 +157,10 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
 }
 
 // Segment length of the 2-D sweeps: 4 nodes per thread (twice the waves) for the
-// FP32 stencil on 16-row tiles when the grid has at most 8 tiles per compute unit, so
+// FP32 stencil on 16-row tiles when the grid has at most 2.5 tiles per compute unit, so
 // that small grids still keep every SIMD busy; 8 otherwise (fewer instructions per
 // node).  FP64 keeps 8: its registers leave no room for the extra waves.
-constexpr int kSmallGridTiles = 2048;
+constexpr int kSmallGridTiles = 640;
 int segment(const hjw_grid* g) {
     if (g->seg_opt) return g->seg_opt;
     return (g->prec != HJW_FP64 && g->tile_rows == 16 && g->nbx * g->nby <= kSmallGridTiles) ? 4

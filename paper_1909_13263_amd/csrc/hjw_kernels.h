@@ -114,6 +114,8 @@ __device__ inline bool plan_in_block(const StageArgs<T, P>& a, int bid, double& 
     if (threadIdx.x < 64) {
         const RangeSlots* sl = static_cast<const RangeSlots*>(a.slots);
         const int k = threadIdx.x;
+        DevState s;
+        if (k == 0) s = a.st[a.par];   // issued with the slot loads: one memory round trip
         double r0 = key_value(sl->key[0][k]), r1 = key_value(sl->key[1][k]);
         double r2 = key_value(sl->key[2][k]), r3 = key_value(sl->key[3][k]);
         unsigned int b = sl->bad[k];
@@ -123,7 +125,6 @@ __device__ inline bool plan_in_block(const StageArgs<T, P>& a, int bid, double& 
         r3 = wave_max(r3);
         b = __any(b != 0u) ? 1u : 0u;
         if (threadIdx.x == 0) {
-            DevState s = a.st[a.par];
             if (step_open(s)) {
                 const double r[4] = {r0, r1, r2, r3};
                 if (b != 0u || !(finite_t(r0) && finite_t(r1) && finite_t(r2) && finite_t(r3))) {
@@ -205,9 +206,16 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
         TL::gather(tid, a, x0, y0, phiL, pnL, gth);
         if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;   // uniform over the workgroup
         TL::make_phi1(tid, a, dt, ax, ay, phiL, gth);
-    } else {
+    } else if (STAGE == kStageMid) {
+        // an edge tile rebuilds phi_1 as it loads: the plan comes first
         if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;
         TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
+    } else {
+        // the other stages load without the step's dt, so the loads go out before the
+        // step record is read and the two latencies overlap; a closed step returns
+        // before anything is written to memory
+        TL::template load<STAGE>(tid, a, x0, y0, 0.0, 0.0, 0.0, phiL, pnL);
+        if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;
     }
     __syncthreads();
     T vm[S], vp[S];

@@ -324,7 +324,7 @@ hipError_t launch_batched_step_s(hjw_server* s, int flip) {
 
 // Launches of at most kSmallLaunch tiles use 4-node segments with the FP32 stencil (twice
 // the waves), as a single grid of that size would; both give the same bits.
-constexpr int kSmallLaunch = 2048;
+constexpr int kSmallLaunch = 640;
 
 template <typename T, typename P>
 hipError_t launch_batched_step(hjw_server* s, int flip) {

@@ -445,8 +445,9 @@ __host__ __device__ inline int64_t resolve(int64_t i, int64_t n, int bc, int& gh
     side = 0;
     if (i >= 0 && i < n) return i;
     if (bc == kBcPeriodic) {
-        int64_t r = i % n;
-        return r < 0 ? r + n : r;
+        // 32-bit remainder: axes hold at most 2^30 nodes and i lies within a tile of them
+        const int r = int(i) % int(n);
+        return r < 0 ? int64_t(r) + n : int64_t(r);
     }
     if (i < 0) {
         ghost = int(-i);
@@ -460,28 +461,41 @@ __host__ __device__ inline int64_t resolve(int64_t i, int64_t n, int bc, int& gh
     return n - 1;
 }
 
-// Value of the stage input at (i, j), ghosts included.  Only one of the two
-// indices is outside the grid on the halo of the plus-shaped stencil; where
-// both are (the unused corner of a partial tile) the value is clamped.
-template <int STAGE, typename T, typename P>
-__host__ __device__ inline P stage_value(const StageArgs<T, P>& a, int64_t i, int64_t j,
-                                         double dt, double ax, double ay) {
+// Where the stage input at (i, j) comes from, ghosts included: idx0 is the node (the
+// edge node for a ghost) and, for a ghost g = 1..3 beyond an edge along one axis, idx1 is
+// its neighbour inside, the value being extrapolated linearly through the two; otherwise
+// idx1 = idx0 and g = 0.  Only one of the two indices is outside the grid on the halo of
+// the plus-shaped stencil; where both are (the unused corner of a partial tile) the value
+// is clamped.
+template <typename T, typename P>
+__host__ __device__ inline void ghost_pair(const StageArgs<T, P>& a, int64_t i, int64_t j,
+                                           int64_t& idx0, int64_t& idx1, int& g) {
     int gx, sx, gy, sy;
     const int64_t ri = resolve(i, a.nx, a.bcx, gx, sx);
     const int64_t rj = resolve(j, a.ny, a.bcy, gy, sy);
-    const P f0 = node_value<STAGE>(a, rj * a.nx + ri, dt, ax, ay);
-    if (gx > 0 && gy == 0) {
-        // linear extrapolation along x through the two edge nodes
-        const int64_t ri1 = ri - sx;  // the neighbour inside
-        const P f1 = node_value<STAGE>(a, rj * a.nx + ri1, dt, ax, ay);
-        return P(f0 + P(gx) * (f0 - f1));
-    }
-    if (gy > 0 && gx == 0) {
-        const int64_t rj1 = rj - sy;
-        const P f1 = node_value<STAGE>(a, rj1 * a.nx + ri, dt, ax, ay);
-        return P(f0 + P(gy) * (f0 - f1));
-    }
-    return f0;
+    const bool ex = gx > 0 && gy == 0, ey = gy > 0 && gx == 0;
+    idx0 = rj * a.nx + ri;
+    idx1 = (ey ? rj - sy : rj) * a.nx + (ex ? ri - sx : ri);
+    g = ex ? gx : (ey ? gy : 0);
+}
+
+template <typename P>
+__host__ __device__ inline P extrapolate(P f0, P f1, int g) {
+    return g ? P(f0 + P(g) * (f0 - f1)) : f0;
+}
+
+// Value of the stage input at (i, j), ghosts included.  Both values are loaded
+// unconditionally (the same node twice when there is no ghost), so that the loads do
+// not wait on a branch.
+template <int STAGE, typename T, typename P>
+__host__ __device__ inline P stage_value(const StageArgs<T, P>& a, int64_t i, int64_t j,
+                                         double dt, double ax, double ay) {
+    int64_t i0, i1;
+    int g;
+    ghost_pair(a, i, j, i0, i1, g);
+    const P f0 = node_value<STAGE>(a, i0, dt, ax, ay);
+    const P f1 = node_value<STAGE>(a, i1, dt, ax, ay);
+    return extrapolate(f0, f1, g);
 }
 
 // ---------------------------------------------------------------- the tile
@@ -504,7 +518,8 @@ struct Tile {
     // Phase 0: phi_s over rows [y0-3, y0+TY+3) x columns [x0-3, x0+TX+3), plus-shaped.
     // Tiles whose halo lies inside the grid index it directly (TX and TY are powers of
     // two, so the index arithmetic is shifts and masks); tiles at an edge resolve each
-    // point through the boundary condition.
+    // point through the boundary condition.  Each thread issues all its loads before it
+    // writes any of them to LDS, so their latencies overlap.
     // The second and third stages also keep phi^n of the tile's own nodes in pnL.
     template <int STAGE>
     __host__ __device__ static void load(int tid, const StageArgs<T, P>& a, int64_t x0,
@@ -512,36 +527,55 @@ struct Tile {
                                          P* pnL) {
         static_assert((TX & (TX - 1)) == 0 && (TY & (TY - 1)) == 0, "power-of-two tile");
         constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
+        // element e of this thread's j-th load; the last round is partial, and its idle
+        // threads load a valid element whose value they drop
+        auto element = [&](int j) {
+            const int e = tid + j * kThreads;
+            return e < kPlusElems ? e : kPlusElems - 1;
+        };
+        P val[kPerThread];
+        P cen[kPerThread];
         if (inside(a, x0, y0)) {
             const int64_t base = (y0 - 3) * a.nx + (x0 - 3);   // global index of phiL[0]
-            for (int e = tid; e < kPlusElems; e += kThreads) {
+#pragma unroll
+            for (int j = 0; j < kPerThread; ++j) {
+                int r, c;
+                plus_node(element(j), r, c);
+                const int64_t idx = base + r * a.nx + c;
+                val[j] = node_value<STAGE>(a, idx, dt, ax, ay);
+                if (kCenter && j * kThreads < TY * TX) cen[j] = a.phi_n[idx];
+            }
+        } else {
+            int64_t i0[kPerThread], i1[kPerThread];
+            int g[kPerThread];
+#pragma unroll
+            for (int j = 0; j < kPerThread; ++j) {
+                int r, c;
+                plus_node(element(j), r, c);
+                ghost_pair(a, x0 + c - 3, y0 + r - 3, i0[j], i1[j], g[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < kPerThread; ++j) {
+                const P f0 = node_value<STAGE>(a, i0[j], dt, ax, ay);
+                const P f1 = node_value<STAGE>(a, i1[j], dt, ax, ay);
+                val[j] = extrapolate(f0, f1, g[j]);
+                if (kCenter && j * kThreads < TY * TX) {
+                    // the tile's own node, clamped into the grid on a partial tile
+                    const int e = element(j);
+                    const int64_t i = x0 + (e % TX), jj = y0 + (e / TX);
+                    const int64_t ic = i < a.nx ? i : a.nx - 1, jc = jj < a.ny ? jj : a.ny - 1;
+                    cen[j] = a.phi_n[jc * a.nx + ic];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int e = tid + j * kThreads;
+            if (e < kPlusElems) {
                 int r, c;
                 plus_node(e, r, c);
-                const int64_t idx = base + r * a.nx + c;
-                phiL[r * PW + c] = node_value<STAGE>(a, idx, dt, ax, ay);
-                if (kCenter && e < TY * TX) pnL[e] = a.phi_n[idx];
-            }
-            return;
-        }
-        constexpr int kRowElems = TY * (TX + 6);   // rows of the tile with the x halo
-        constexpr int kColElems = 6 * TX;          // the three rows above and below
-        for (int e = tid; e < kRowElems + kColElems; e += kThreads) {
-            int r, c;
-            if (e < kRowElems) {
-                r = e / (TX + 6) + 3;
-                c = e % (TX + 6);
-            } else {
-                const int f = e - kRowElems;
-                const int rr = f / TX;                 // 0..5
-                r = rr < 3 ? rr : TY + rr;             // 0,1,2, TY+3..TY+5
-                c = f % TX + 3;
-            }
-            phiL[r * PW + c] = stage_value<STAGE>(a, x0 + c - 3, y0 + r - 3, dt, ax, ay);
-        }
-        if (kCenter) {
-            for (int e = tid; e < TY * TX; e += kThreads) {
-                const int64_t i = x0 + e % TX, j = y0 + e / TX;
-                if (i < a.nx && j < a.ny) pnL[e] = a.phi_n[j * a.nx + i];
+                phiL[r * PW + c] = val[j];
+                if (kCenter && e < TY * TX) pnL[e] = cen[j];
             }
         }
     }
