@@ -69,10 +69,15 @@ typedef enum {
                                   hjw_kernel_times reports.  0 (default): off. */
     HJW_OPT_TILE_ROWS = 2,     /* 2-D tile height: 16 (default: 64 x 16 nodes) or 32 (64 x 32
                                   nodes, 8-node segments only).  Results are identical. */
-    HJW_OPT_SEGMENT = 3        /* nodes each thread marches in the 2-D sweeps: 0 (default)
+    HJW_OPT_SEGMENT = 3,       /* nodes each thread marches in the 2-D sweeps: 0 (default)
                                   automatic, 4 (FP32 stencil, 16-row tiles: 512 threads per
                                   tile) or 8 (256 threads per 16-row tile).  Results are
                                   identical. */
+    HJW_OPT_PLAN = 4           /* where a 2-D step's dissipation and time step are computed:
+                                  0 (default) automatic, 1 in every workgroup of the second
+                                  stage, 2 in a one-wave launch of its own between the first
+                                  and second stages (chosen automatically above 2048 tiles).
+                                  Results are identical. */
 } hjw_option;
 
 typedef struct hjw_grid hjw_grid;
@@ -127,15 +132,17 @@ hjw_status hjw_get_info(const hjw_grid *g, hjw_info *info);
 
 hjw_status hjw_set_option(hjw_grid *g, int option, int64_t value);
 
-/* With HJW_OPT_KERNEL_EVENTS on: total milliseconds and launch counts of the four
+/* With HJW_OPT_KERNEL_EVENTS on: total milliseconds and launch counts of the
  * kernels of a step since the option was switched on, in the order
- * [0] derivatives of phi^n and block ranges, [1] dissipation and time step,
- * [2] second stage, [3] third stage.  ms[4] and count[4] are caller-owned. */
+ * [0] derivatives of phi^n and range slots, [1] the plan launch (dissipation and
+ * time step; none where the second stage plans for itself), [2] second stage,
+ * [3] third stage.  ms[4] and count[4] are caller-owned. */
 hjw_status hjw_kernel_times(const hjw_grid *g, double *ms, int64_t *count);
 
-/* Average duration in milliseconds of each of the three stage kernels of a step
- * (ms[0] first, ms[1] second, ms[2] third stage), each launched reps times back to
- * back on the grid's stream between two HIP events, on the grid's current phi.
+/* Average duration in milliseconds of each kernel of a step (ms[0] first stage,
+ * ms[1] the plan launch, 0 where the second stage plans for itself, ms[2] second,
+ * ms[3] third stage; ms holds 4 values, caller-owned), each launched reps times back
+ * to back on the grid's stream between two HIP events, on the grid's current phi.
  * Takes one real step first; afterwards phi is undefined and must be set again
  * (hjw_set_phi) before stepping. */
 hjw_status hjw_time_kernels(hjw_grid *g, int reps, double *ms);

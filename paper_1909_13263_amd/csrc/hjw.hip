@@ -71,6 +71,7 @@ struct hjw_grid {
     int nbx = 0, nby = 0;
     int tile_rows = 16;  // 2-D tile height (16 or 32)
     int seg_opt = 0;     // nodes per thread in the 2-D sweeps: 0 automatic, 4 or 8
+    int plan_opt = 0;    // step plan: 0 automatic, 1 in every workgroup, 2 own launch
 
     // host mirror
     DevState* pinned = nullptr;  // pinned host copy of the device state
@@ -123,6 +124,16 @@ void layout(const hjw_grid* g, size_t* off_phi2, size_t* off_flux, size_t* off_p
     *total = o;
 }
 
+// The step plan gets a launch of its own (one wave between the first and second stage
+// kernels) on grids of more than kPlanLaunchTiles tiles; on smaller grids the extra
+// launch costs more than every workgroup planning for itself.
+constexpr int kPlanLaunchTiles = 2048;
+bool plan_launch(const hjw_grid* g) {
+    if (g->dim != 2) return false;
+    if (g->plan_opt) return g->plan_opt == 2;
+    return g->nbx * g->nby > kPlanLaunchTiles;
+}
+
 template <typename T, typename P>
 StageArgs<T, P> make_args(const hjw_grid* g) {
     StageArgs<T, P> a{};
@@ -153,6 +164,7 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     a.nby = g->nby;
     a.remap = (g->dim == 2 && (g->nbx * g->nby) % 8 == 0) ? 1 : 0;
     a.dim = g->dim;
+    a.plan_ready = plan_launch(g) ? 1 : 0;
     return a;
 }
 
@@ -206,6 +218,13 @@ hipError_t enqueue_step_typed(hjw_grid* g) {
     g->par ^= 1;   // every enqueued step moves the current record to the other slot
     hipError_t e = timed(g, 0, [&] { return launch_stage<T, P, kStagePre>(g, a); });
     if (e != hipSuccess) return e;
+    if (a.plan_ready) {
+        e = timed(g, 1, [&] {
+            hipLaunchKernelGGL((k_plan<T, P>), dim3(1), dim3(64), 0, g->stream, a);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+    }
     a.out = static_cast<P*>(g->phi2);
     e = timed(g, 2, [&] { return launch_stage<T, P, kStageMid>(g, a); });
     if (e != hipSuccess) return e;
@@ -224,12 +243,17 @@ hipError_t enqueue_step(hjw_grid* g) {
     }
 }
 
-// Stage kernel k (0 first, 1 second, 2 third) against the records of the current parity.
+// Kernel k of a step (0 first stage, 1 plan, 2 second, 3 third stage) against the
+// records of the current parity.
 template <typename T, typename P>
 hipError_t launch_kind(const hjw_grid* g, int k) {
     StageArgs<T, P> a = make_args<T, P>(g);
     if (k == 0) return launch_stage<T, P, kStagePre>(g, a);
     if (k == 1) {
+        hipLaunchKernelGGL((k_plan<T, P>), dim3(1), dim3(64), 0, g->stream, a);
+        return hipGetLastError();
+    }
+    if (k == 2) {
         a.out = static_cast<P*>(g->phi2);
         return launch_stage<T, P, kStageMid>(g, a);
     }
@@ -562,6 +586,12 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
         if (!g->use_graph) drop_graph(g);
         return HJW_OK;
     }
+    if (option == HJW_OPT_PLAN) {
+        if (value < 0 || value > 2) return fail(HJW_EINVAL, "plan option must be 0, 1 or 2");
+        g->plan_opt = int(value);
+        drop_graph(g);
+        return HJW_OK;
+    }
     if (option == HJW_OPT_SEGMENT) {
         if (value != 0 && value != 4 && value != 8)
             return fail(HJW_EINVAL, "segment must be 0 (automatic), 4 or 8");
@@ -616,7 +646,10 @@ hjw_status hjw_time_kernels(hjw_grid* g, int reps, double* ms) {
     HIP_TRY(hipEventCreate(&e1));
     hipError_t err = hipSuccess;
     g->par ^= 1;   // launch against the records of the step just taken
-    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+    const bool plan = plan_launch(g);
+    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+        ms[k] = 0.0;
+        if (k == 1 && !plan) continue;   // the plan runs inside the second stage
         err = hipEventRecord(e0, g->stream);
         for (int r = 0; r < reps && err == hipSuccess; ++r) {
             switch (g->prec) {

@@ -169,7 +169,15 @@ __device__ inline bool stage_entry(const StageArgs<T, P>& a, int bid, double& dt
                                    double& ay) {
     dt = ax = ay = 0.0;
     if (STAGE == kStagePre) return step_open(a.st[a.par]);
-    if (STAGE == kStageMid) return plan_in_block(a, bid, dt, ax, ay);
+    if (STAGE == kStageMid) {
+        if (!a.plan_ready) return plan_in_block(a, bid, dt, ax, ay);
+        const DevState& n = a.st[a.par ^ 1];
+        if (!n.active) return false;
+        dt = n.dt;
+        ax = n.alpha_x;
+        ay = n.alpha_y;
+        return true;
+    }
     if (STAGE == kStageLast) {
         const DevState& n = a.st[a.par ^ 1];
         if (!n.active) return false;
@@ -266,6 +274,14 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     } else if (STAGE == kStageLast) {
         if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
     }
+}
+
+// The step plan as a launch of its own (one wave): on large grids, planning once
+// costs less than planning in every workgroup of the second stage.
+template <typename T, typename P>
+__global__ __launch_bounds__(64) void k_plan(StageArgs<T, P> a) {
+    double dt, ax, ay;
+    (void)plan_in_block(a, 0, dt, ax, ay);
 }
 
 static __global__ void k_set_target(DevState* st, double t_final, double cfl, int64_t steps_left) {

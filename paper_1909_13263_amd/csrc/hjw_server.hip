@@ -39,7 +39,8 @@ namespace hjw {
 template <typename T, typename P, int STAGE, int S>
 __global__ __launch_bounds__(threads2d(16, S)) void k_stage2d_batch(const StageArgs<T, P>* table,
                                                                    const int* tile_start,
-                                                                   const int* ngrids, int flip) {
+                                                                   const int* ngrids, int flip,
+                                                                   int plan_ready) {
     const int ng = *ngrids;
     const int b = int(blockIdx.x % 8u * (gridDim.x / 8u) + blockIdx.x / 8u);
     if (ng <= 0 || b >= tile_start[ng]) return;
@@ -53,10 +54,22 @@ __global__ __launch_bounds__(threads2d(16, S)) void k_stage2d_batch(const StageA
     }
     StageArgs<T, P> a = table[lo];
     a.par ^= flip;
+    a.plan_ready = plan_ready;
     // the second stage writes phi_2, the third phi^{n+1} over phi^n
     if (STAGE == kStageMid) a.out = const_cast<P*>(a.phi_s);
     if (STAGE == kStageLast) a.out = const_cast<P*>(a.phi_n);
     stage_tile2d<T, P, STAGE, 16, S>(a, b - tile_start[lo]);
+}
+
+// The step plans of all admitted solves, one wave each (workgroup g plans solve g).
+template <typename T, typename P>
+__global__ __launch_bounds__(64) void k_plan_batch(const StageArgs<T, P>* table,
+                                                   const int* ngrids, int flip) {
+    if (int(blockIdx.x) >= *ngrids) return;
+    StageArgs<T, P> a = table[blockIdx.x];
+    a.par ^= flip;
+    double dt, ax, ay;
+    (void)plan_in_block(a, 0, dt, ax, ay);
 }
 
 // A newly admitted solve: record 0 is current (t = 0, target t_final), slots empty.
@@ -305,20 +318,31 @@ void write_table(hjw_server* s) {
     s->launch_tiles = launch_size(tiles);
 }
 
+// Launches of more than kPlanLaunchTiles tiles plan every solve's step in a launch of its
+// own (one wave per solve) instead of in every workgroup of the second stage.
+constexpr int kPlanLaunchTiles = 2048;
+
 template <typename T, typename P, int S>
 hipError_t launch_batched_step_s(hjw_server* s, int flip) {
     const StageArgs<T, P>* tab = static_cast<const StageArgs<T, P>*>(s->d_table);
     const dim3 grid(unsigned(s->launch_tiles)), block(threads2d(kTY, S));
+    const int plan = s->launch_tiles > kPlanLaunchTiles ? 1 : 0;
     hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre, S>), grid, block, 0, s->stream, tab,
-                       s->d_tile_start, s->d_ngrids, flip);
+                       s->d_tile_start, s->d_ngrids, flip, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (plan) {
+        hipLaunchKernelGGL((k_plan_batch<T, P>), dim3(unsigned(s->max_active)), dim3(64), 0,
+                           s->stream, tab, s->d_ngrids, flip);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageMid, S>), grid, block, 0, s->stream, tab,
-                       s->d_tile_start, s->d_ngrids, flip);
+                       s->d_tile_start, s->d_ngrids, flip, plan);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageLast, S>), grid, block, 0, s->stream, tab,
-                       s->d_tile_start, s->d_ngrids, flip);
+                       s->d_tile_start, s->d_ngrids, flip, 0);
     return hipGetLastError();
 }
 

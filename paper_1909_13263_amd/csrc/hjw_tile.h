@@ -417,6 +417,7 @@ struct StageArgs {
     int nbx, nby;
     int remap;        // nonzero: spread neighbouring tiles over one XCD
     int dim;
+    int plan_ready;   // nonzero: the step plan was published by its own launch
 };
 
 // Stage input at a node inside the grid.

@@ -23,7 +23,8 @@ OPT_USE_GRAPH = 0
 OPT_KERNEL_EVENTS = 1
 OPT_TILE_ROWS = 2
 OPT_SEGMENT = 3
-KERNEL_NAMES = ("pre", "finalize", "mid", "last")
+OPT_PLAN = 4
+KERNEL_NAMES = ("pre", "plan", "mid", "last")
 
 PREC_NAMES = {"fp64": FP64, "fp32_mixed": FP32_MIXED, "fp32": FP32}
 
@@ -222,11 +223,12 @@ class Grid:
         return {KERNEL_NAMES[k]: (ms[k], int(cnt[k])) for k in range(4)}
 
     def time_kernels(self, reps=50):
-        """Average ms per launch of the three stage kernels, reps back-to-back launches each
-        between HIP events.  Leaves phi undefined (set it again before stepping)."""
-        ms = (ctypes.c_double * 3)()
+        """Average ms per launch of the kernels of a step ({pre, plan, mid, last}; plan is
+        0 where the second stage plans for itself), reps back-to-back launches each between
+        HIP events.  Leaves phi undefined (set it again before stepping)."""
+        ms = (ctypes.c_double * 4)()
         _check(lib().hjw_time_kernels(self._h, int(reps), ms))
-        return {"pre": ms[0], "mid": ms[1], "last": ms[2]}
+        return {"pre": ms[0], "plan": ms[1], "mid": ms[2], "last": ms[3]}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -93,6 +93,8 @@ def test_segment_and_tile_options_are_validated():
     assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 0) == hjw.OK
     assert L.hjw_set_option(h32, hjw.OPT_TILE_ROWS, 32) == hjw.OK
     assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 4) == hjw.EINVAL
+    assert L.hjw_set_option(h32, hjw.OPT_PLAN, 3) == hjw.EINVAL
+    assert L.hjw_set_option(h32, hjw.OPT_PLAN, 2) == hjw.OK
     L.hjw_grid_destroy(h64)
     L.hjw_grid_destroy(h32)
 

@@ -217,6 +217,23 @@ def test_segment_lengths_give_identical_results(prec, shape):
     assert np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_plan_launch_gives_identical_results(prec):
+    """The step plan computed in every workgroup of the second stage or in a launch of its
+    own (HJW_OPT_PLAN) is the same computation on the same slots: identical bits."""
+    pr = W.negcos2d(300, 0.05, ny=230)
+    out = []
+    for mode in (1, 2):
+        g = hjw.grid_for(pr, prec)
+        g.set_option(hjw.OPT_PLAN, mode)
+        g.set_phi(pr.phi0())
+        info = g.step_to(pr.t_final, pr.cfl)
+        out.append((info.steps, info.last_dt, g.get_phi()))
+        g.close()
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 def test_transpose_symmetry_on_gpu():
     """Dimension by dimension: a transposed problem gives the transposed result, bit for
     bit: the row and column sweeps run the same arithmetic, and the products of the
@@ -300,7 +317,8 @@ def test_time_kernels_contract():
     g = hjw.grid_for(pr, MIXED)
     g.set_phi(pr.phi0())
     ms = g.time_kernels(reps=3)
-    assert all(v > 0 for v in ms.values()), ms
+    assert ms["plan"] == 0.0                # a 256^2 grid plans inside the second stage
+    assert all(ms[k] > 0 for k in ("pre", "mid", "last")), ms
     with pytest.raises(hjw.HJWError) as e:
         g.step_to(0.01, 0.5)
     assert e.value.code == hjw.ESTATE
