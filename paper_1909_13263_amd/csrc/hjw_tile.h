@@ -613,17 +613,26 @@ struct Tile {
     __host__ __device__ static void gather(int tid, const StageArgs<T, P>& a, int64_t x0,
                                            int64_t y0, P* phiL, P* pnL, Gathered& g) {
         const int64_t base = (y0 - 3) * a.nx + (x0 - 3);
+        // every load first (the idle threads of the last round load a valid element),
+        // then the LDS writes
+        P pn[kPerThread];
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int e = tid + j * kThreads;
+            int r, c;
+            plus_node(e < kPlusElems ? e : kPlusElems - 1, r, c);
+            const int64_t idx = base + r * a.nx + c;
+            pn[j] = a.phi_n[idx];
+            g.f[j] = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
+        }
 #pragma unroll
         for (int j = 0; j < kPerThread; ++j) {
             const int e = tid + j * kThreads;
             if (e < kPlusElems) {
                 int r, c;
                 plus_node(e, r, c);
-                const int64_t idx = base + r * a.nx + c;
-                const P pn = a.phi_n[idx];
-                phiL[r * PW + c] = pn;
-                g.f[j] = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
-                if (e < TY * TX) pnL[e] = pn;
+                phiL[r * PW + c] = pn[j];
+                if (e < TY * TX) pnL[e] = pn[j];
             }
         }
     }
