@@ -511,10 +511,15 @@ hjw_status hjw_step_to(hjw_grid* g, double t_final, double cfl, int64_t max_step
     if (s != HJW_OK) return s;
     int64_t taken = 0;
     while (g->last.t < t_final && taken < limit && !g->last.bad) {
-        int64_t n = 1;
+        // Steps enqueued before the next read of the step state: one graph's worth
+        // while dt is unknown, else the estimate from the last dt plus a margin (dt
+        // shrinks as the dissipation grows).  Surplus steps find t_final reached and
+        // exit at once; a short count costs a round trip to the host.
+        int64_t n = kGraphSteps;
         if (g->last.dt > 0.0) {
             const double est = std::ceil((t_final - g->last.t) / g->last.dt);
-            n = est > 1.0 ? int64_t(std::min(est, double(kMaxBatch))) : 1;
+            const double want = est + std::max(2.0, std::ceil(est / 32.0));
+            n = int64_t(std::min(std::max(want, 1.0), double(kMaxBatch)));
         }
         n = std::min(n, limit - taken);
         s = enqueue_steps(g, n);

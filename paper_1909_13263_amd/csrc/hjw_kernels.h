@@ -214,16 +214,10 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
         TL::gather(tid, a, x0, y0, phiL, pnL, gth);
         if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;   // uniform over the workgroup
         TL::make_phi1(tid, a, dt, ax, ay, phiL, gth);
-    } else if (STAGE == kStageMid) {
-        // an edge tile rebuilds phi_1 as it loads: the plan comes first
+    } else {
+        // a step past its end returns before loading anything
         if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;
         TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
-    } else {
-        // the other stages load without the step's dt, so the loads go out before the
-        // step record is read and the two latencies overlap; a closed step returns
-        // before anything is written to memory
-        TL::template load<STAGE>(tid, a, x0, y0, 0.0, 0.0, 0.0, phiL, pnL);
-        if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;
     }
     __syncthreads();
     T vm[S], vp[S];

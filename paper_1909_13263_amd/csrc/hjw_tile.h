@@ -25,11 +25,11 @@
 //   (F_{i-1}, C_i) for k = 0, 1, 2 of phi_{x,i}^-; by the mirror symmetry the same
 //   three cell lengths serve phi_{x,i-1}^+ with their weights reversed.  So each
 //   cell's three lengths are computed once and used twice.
-//   L = h * M(a, b), M = mean of sqrt(1+s^2) for s between the end values; M is
+//   L = h * M(a, b), M = mean of sqrt(1+s^2) for s between the end values; M^2 is
 //   evaluated from a Taylor series about the midpoint when the pair is close
-//   (relative half-gap below TAU) and from the antiderivative otherwise.
-//   With t_k = (eps/h^2 + M_k^2)^2 the weights become products of the other two
-//   t's (one division per side); in FP32 the t's are first scaled by 1/max t.
+//   (relative half-gap below TAU; no square root needed) and from the antiderivative
+//   otherwise.  With t_k = (eps/h^2 + M_k^2)^2 the weights become products of the
+//   other two t's (one division per side); in FP32 the t's are first scaled by 1/max t.
 //   The weighted sum is formed as the central candidate plus a correction made
 //   of two third differences (see sweep()).
 #pragma once
@@ -87,10 +87,6 @@ constexpr int kPartialStride = 5;
 // ---------------------------------------------------------------- math helpers
 // Host and device overloads of the few primitives whose fast device form is a
 // builtin; everything else is ordinary C++ arithmetic.
-__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__host__ inline float rsqrt_t(float x) { return 1.0f / std::sqrt(x); }
-__device__ inline double rsqrt_t(double x) { return rsqrt(x); }
-__host__ inline double rsqrt_t(double x) { return 1.0 / std::sqrt(x); }
 __device__ inline float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __host__ inline float rcp_t(float x) { return 1.0f / x; }
 __host__ __device__ inline double rcp_t(double x) { return 1.0 / x; }
@@ -130,31 +126,29 @@ template <typename T> struct SeriesCfg;
 template <> struct SeriesCfg<double> { static constexpr double tau2 = 4.0e-4; };
 template <> struct SeriesCfg<float> { static constexpr float tau2 = 1.0e-2f; };
 
-// Twice the mean of sqrt(1+s^2) between a and b, from the sum sg = a + b and the
-// difference dl = b - a, by the midpoint expansion
-//   2M = sqrt(q4) (1 + g^2 (2/3 + g^2 (2/5 (sg^2-1) + g^2 2/7 (sg^4 - 6 sg^2 + 2)))),
+// The square of twice the mean of sqrt(1+s^2) between a and b, from the sum sg = a + b
+// and the difference dl = b - a, by the midpoint expansion
+//   2M = sqrt(q4) X,  X = 1 + g^2 (2/3 + g^2 (2/5 (sg^2-1) + g^2 2/7 (sg^4 - 6 sg^2 + 2))),
 //   q4 = 4 + sg^2, g = dl / q4
-// (the Taylor series of the mean about m = sg/2 with y = (h/(1+m^2))^2 = 4 g^2).
-// x receives the relative gap dl / sqrt(q4).
-__host__ __device__ inline double mean2_series(double sg, double dl, double q4, double& x) {
-    const double r = rsqrt_t(q4);
-    const double sq = q4 * r;
-    x = dl * r;
-    const double g = x * r;
+// (the Taylor series of the mean about m = sg/2 with y = (h/(1+m^2))^2 = 4 g^2), so
+// (2M)^2 = q4 X^2 needs no square root.  xx receives the squared relative gap dl^2 / q4.
+__host__ __device__ inline double mean2sq_series(double sg, double dl, double q4, double& xx) {
+    const double g = dl / q4;
+    xx = dl * g;
     const double g2 = g * g;
     const double s2 = sg * sg;
     const double inner =
         (2.0 / 3.0) + g2 * (0.4 * (s2 - 1.0) + g2 * ((2.0 / 7.0) * (s2 * (s2 - 6.0) + 2.0)));
-    return sq + sq * g2 * inner;
+    const double X = 1.0 + g2 * inner;
+    return (q4 * X) * X;
 }
-__host__ __device__ inline float mean2_series(float sg, float dl, float q4, float& x) {
-    const float r = rsqrt_t(q4);
-    const float sq = q4 * r;
-    x = dl * r;
-    const float g = x * r;
+__host__ __device__ inline float mean2sq_series(float sg, float dl, float q4, float& xx) {
+    const float g = dl * rcp_t(q4);
+    xx = dl * g;
     const float g2 = g * g;
     const float inner = (2.0f / 3.0f) + g2 * (0.4f * (sg * sg - 1.0f));
-    return sq + sq * g2 * inner;
+    const float X = 1.0f + g2 * inner;
+    return (q4 * X) * X;
 }
 
 // Antiderivative of sqrt(1+s^2): (s sqrt(1+s^2) + asinh s) / 2.
@@ -187,38 +181,44 @@ __host__ __device__ inline float wdiv<float>(float num, float den) {
     return num * rcp_t(den);
 }
 
-// Twice the means for the three pairs of one cell: (c0, b1), (c0, c1), (f0, c1).
-// A pair whose relative half-gap is not small takes the antiderivative instead;
-// the wave takes that branch only when one of its lanes needs it.
+// Squares of the doubled means for the three pairs of one cell: (c0, b1), (c0, c1),
+// (f0, c1).  A pair whose relative half-gap is not small takes the antiderivative
+// instead; the wave takes that branch only when one of its lanes needs it.
 template <typename T>
-__host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA, T& MB, T& MC) {
+__host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA2, T& MB2, T& MC2) {
     const T tau2 = SeriesCfg<T>::tau2;
     const T sA = c0 + b1, dA = b1 - c0;
     const T sB = c0 + c1, dB = c1 - c0;
     const T sC = f0 + c1, dC = c1 - f0;
     const T qA = sA * sA + T(4), qB = sB * sB + T(4), qC = sC * sC + T(4);
-    // half-gap dl/2 against tau sqrt(1 + m^2) = tau sqrt(q4)/2: wide when x^2 >= tau^2
+    // half-gap dl/2 against tau sqrt(1 + m^2) = tau sqrt(q4)/2: wide when dl^2/q4 >= tau^2
     T xA, xB, xC;
-    MA = mean2_series(sA, dA, qA, xA);
-    MB = mean2_series(sB, dB, qB, xB);
-    MC = mean2_series(sC, dC, qC, xC);
-    xA *= xA;
-    xB *= xB;
-    xC *= xC;
+    MA2 = mean2sq_series(sA, dA, qA, xA);
+    MB2 = mean2sq_series(sB, dB, qB, xB);
+    MC2 = mean2sq_series(sC, dC, qC, xC);
     if (any_lane(fmax(xA, fmax(xB, xC)) >= tau2)) {
         const T Pc0 = prim(c0), Pb1 = prim(b1), Pc1 = prim(c1), Pf0 = prim(f0);
-        if (xA >= tau2) MA = wdiv(T(2) * (Pb1 - Pc0), dA);
-        if (xB >= tau2) MB = wdiv(T(2) * (Pc1 - Pc0), dB);
-        if (xC >= tau2) MC = wdiv(T(2) * (Pc1 - Pf0), dC);
+        if (xA >= tau2) {
+            const T M = wdiv(T(2) * (Pb1 - Pc0), dA);
+            MA2 = M * M;
+        }
+        if (xB >= tau2) {
+            const T M = wdiv(T(2) * (Pc1 - Pc0), dB);
+            MB2 = M * M;
+        }
+        if (xC >= tau2) {
+            const T M = wdiv(T(2) * (Pc1 - Pf0), dC);
+            MC2 = M * M;
+        }
     }
 }
 
 // Products of the weight denominators: with t_k = (eps/h^2 + M_k^2)^2 (up to a
 // common factor), omega_k of eq. (WLOC1) is proportional to d_k times the product
-// of the other two t's.  Inputs are the doubled means and eps4 = 4 eps / h^2.
-__host__ __device__ inline void weight_products(double MA, double MB, double MC, double eps4,
+// of the other two t's.  Inputs are the squared doubled means and eps4 = 4 eps / h^2.
+__host__ __device__ inline void weight_products(double MA2, double MB2, double MC2, double eps4,
                                                 double& pAB, double& pAC, double& pBC) {
-    double tA = eps4 + MA * MA, tB = eps4 + MB * MB, tC = eps4 + MC * MC;
+    double tA = eps4 + MA2, tB = eps4 + MB2, tC = eps4 + MC2;
     tA *= tA;
     tB *= tB;
     tC *= tC;
@@ -227,9 +227,9 @@ __host__ __device__ inline void weight_products(double MA, double MB, double MC,
     pBC = tB * tC;
 }
 // FP32: the t's are first scaled by 1/max t so that no product overflows.
-__host__ __device__ inline void weight_products(float MA, float MB, float MC, float eps4,
+__host__ __device__ inline void weight_products(float MA2, float MB2, float MC2, float eps4,
                                                 float& pAB, float& pAC, float& pBC) {
-    float tA = eps4 + MA * MA, tB = eps4 + MB * MB, tC = eps4 + MC * MC;
+    float tA = eps4 + MA2, tB = eps4 + MB2, tC = eps4 + MC2;
     const float s = rcp_t(fmaxf(tA, fmaxf(tB, tC)));
     tA *= s;
     tB *= s;
@@ -275,10 +275,10 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
         const T c1 = e3 * ih;                 // C_i
         const T b1 = B1 * ih;                 // B_i
         const T f0 = F0 * ih;                 // F_{i-1}
-        T MA, MB, MC;
-        cell_means(c0, b1, c1, f0, MA, MB, MC);
+        T MA2, MB2, MC2;
+        cell_means(c0, b1, c1, f0, MA2, MB2, MC2);
         T pAB, pAC, pBC;
-        weight_products(MA, MB, MC, eps4, pAB, pAC, pBC);
+        weight_products(MA2, MB2, MC2, eps4, pAB, pAC, pBC);
         const T D3a = B1 - e3;                // a - 3b + 3c - d
         const T D3b = F0 - e2;                // b - 3c + 3d - e
         // numerators and denominators below are six times those of the weighted sums
