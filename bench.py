@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0, help="16 or 32 (0: library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
+    ap.add_argument("--no-jp", action="store_true", help="skip the WENO-JP comparison solve")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 error of the full-size configurations")
     ap.add_argument("--serve-requests", type=int, default=2048)
@@ -109,9 +110,9 @@ def calibrate_copy():
     return 0
 
 
-def time_solves(hjw, pr, prec, phi_dev, steps, warmup, tile_rows=0):
+def time_solves(hjw, pr, prec, phi_dev, steps, warmup, tile_rows=0, scheme=0):
     import torch
-    g = hjw.grid_for(pr, prec)
+    g = hjw.grid_for(pr, prec, scheme=scheme)
     if tile_rows:
         g.set_option(hjw.OPT_TILE_ROWS, tile_rows)
     info = None
@@ -149,10 +150,49 @@ def cpu_baseline(pr, seconds):
             break
     wall = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pr.cells * 3 * steps / wall, "unit": "cell-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{steps} RK3 steps of the {pr.shape[1]}x{pr.shape[0]} grid from t=0 "
-                      f"({wall:.1f} s, FP64 C, OpenMP over grid lines)"}
+    out = {"value": pr.cells * 3 * steps / wall, "unit": "cell-updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{steps} RK3 steps of the {pr.shape[1]}x{pr.shape[0]} grid from t=0 "
+                     f"({wall:.1f} s, FP64 C, OpenMP over grid lines)",
+           "cpu_model": cpu_model()}
+    one = single_core_rate(pr, max(2.0, seconds / 4))
+    if one is not None:
+        out["single_core_value"] = one
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_core_rate(pr, seconds):
+    """The same oracle steps on one thread, in a child process (OMP_NUM_THREADS=1)."""
+    import subprocess
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import oracle as O\n"
+        "from paper_1909_13263_amd import workloads as W\n"
+        "pr = W.burgers2d(%d, %r)\n"
+        "prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc)\n"
+        "phi = pr.phi0(); t = 0.0; n = 0; t0 = time.perf_counter()\n"
+        "while time.perf_counter() - t0 < %r and t < pr.t_final:\n"
+        "    phi, info = O.rk3_step(prob, phi, t, pr.t_final, pr.cfl); t = info.t; n += 1\n"
+        "print(json.dumps({'rate': pr.cells * 3 * n / (time.perf_counter() - t0)}))\n"
+    ) % (ROOT, pr.shape[1], pr.t_final, seconds)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=seconds * 4 + 60)
+        return json.loads(r.stdout.strip().splitlines()[-1])["rate"] if r.returncode == 0 else None
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
 
 
 def accuracy_cases():
@@ -180,8 +220,9 @@ def solve_once(hjw, pr, prec):
 
 def accuracy(hjw):
     """Error of the FP32 paths against FP64 on the same GPU, whose results match the
-    FP64 oracle to 1e-12 of max|phi| (the parity tests): L-inf, and L1 as the grid mean of
-    |error| (the domain-normalised integral), both also relative to max|phi|."""
+    FP64 oracle to 1e-12 of max|phi| (the parity tests): L-inf; L1 as the grid mean of
+    |error| and as the domain integral dx dy sum|error|; L-inf and mean L1 also relative
+    to max|phi|."""
     out = {}
     for label, pr, precs in accuracy_cases():
         ref, info = solve_once(hjw, pr, hjw.FP64)
@@ -191,11 +232,38 @@ def accuracy(hjw):
             phi, pinfo = solve_once(hjw, pr, prec)
             err = np.abs(phi - ref)
             name = {hjw.FP32_MIXED: "fp32_stencil", hjw.FP32: "fp32_storage"}[prec]
+            cell = float(np.prod(pr.spacing))
             row[name] = {"linf": float(err.max()), "l1": float(err.mean()),
+                         "l1_integral": float(err.sum()) * cell,
                          "linf_rel": float(err.max()) / scale, "l1_rel": float(err.mean()) / scale,
                          "steps": pinfo.steps}
         out[label] = row
     return out
+
+
+def beyond_mall(hjw, W, steps=3):
+    """A grid whose working set (phi, stage buffer, flux records: 28 B per node) exceeds
+    the 256 MB Infinity Cache: 4096^2 Burgers, FP32 stencil, whole solves to 0.1/pi^2."""
+    import torch
+    pr = W.burgers2d(4096, 0.1 / math.pi**2)
+    phi_dev = torch.from_numpy(pr.phi0()).to("cuda")
+    g = hjw.grid_for(pr, hjw.FP32_MIXED)
+    g.set_phi(phi_dev)
+    info = g.step_to(pr.t_final, pr.cfl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.set_phi(phi_dev)
+        info = g.step_to(pr.t_final, pr.cfl)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    g.close()
+    rate = pr.cells * 3 * info.steps / wall
+    step_bytes = sum(kernel_bytes_per_cell(8, 4).values()) / 3.0   # per node-stage
+    return {"grid": "4096x4096 burgers2d, t=0.1/pi^2", "working_set_MB": pr.cells * 28 / 1e6,
+            "rk_steps": info.steps, "ms_per_solve": wall * 1e3, "cell_updates_per_s": rate,
+            "sustained_GBps": rate * step_bytes / 1e9,
+            "sustained_frac": rate * step_bytes / 1e9 / HBM_PEAK_GBS}
 
 
 def served_stream(args, hjw):
@@ -317,8 +385,17 @@ def main():
                         "rk_steps": r["rk_steps"],
                         "kernel_ms": r["kernels"]}
         line["fp32_speedup_over_fp64"] = main_res["cell_updates_per_s"] / r["cell_updates_per_s"]
+    if not args.no_jp:
+        # the paper's comparison scheme on the same workload (Jiang-Peng indicators)
+        wall, info, times = time_solves(hjw, pr, hjw.FP32_MIXED, phi_dev, args.steps, args.warmup,
+                                        args.tile_rows, scheme=hjw.WENO_JP)
+        line["weno_jp"] = {"value": cells * 3 * info.steps * args.steps / wall,
+                           "ms_per_step": 1e3 * wall / args.steps, "rk_steps": info.steps,
+                           "kernel_ms": times,
+                           "time_ratio_jp_over_l": (1e3 * wall / args.steps) / main_res["ms_per_solve"]}
     if not args.no_accuracy:
         line["fp32_error_vs_fp64"] = accuracy(hjw)
+        line["beyond_infinity_cache"] = beyond_mall(hjw, W)
     if not args.no_serve:
         line["served"] = served_stream(args, hjw)
     if not args.no_cpu_baseline:

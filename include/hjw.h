@@ -52,6 +52,13 @@ typedef enum { HJW_BC_PERIODIC = 0, HJW_BC_EXTRAP = 1 } hjw_bc;
  *                   evaluated in FP64 before rounding). */
 typedef enum { HJW_FP64 = 0, HJW_FP32_MIXED = 1, HJW_FP32 = 2 } hjw_prec;
 
+/* Smoothness indicators of the fifth-order reconstruction (the candidates, linear
+ * weights (1, 6, 3)/10, eps = 1e-6 and the weight formula of eq. (WLOC1) are shared):
+ *   HJW_WENO_L   the paper's arc-length indicators, Section 2 Step 4 (default);
+ *   HJW_WENO_JP  Jiang and Peng's indicators, the scheme the paper compares with in
+ *                Section 3 (Tables 1-4, right halves). */
+typedef enum { HJW_WENO_L = 0, HJW_WENO_JP = 1 } hjw_scheme;
+
 /* Built-in Hamiltonians H(u, v), u = phi_x, v = phi_y (v = 0 in 1-D):
  *   LINEAR   p[0]*u + p[1]*v                    (Example 3.1)
  *   BURGERS  (p[0]*u + p[1]*v + p[2])^2 / 2     (Examples 3.3, 3.6)
@@ -107,6 +114,10 @@ hjw_status hjw_bind(hjw_grid *g, void *dev_workspace, size_t bytes, void *hip_st
 
 /* Choose the Hamiltonian (see hjw_ham) and its parameters (nparams <= 4). */
 hjw_status hjw_set_hamiltonian(hjw_grid *g, int kind, const double *params, int nparams);
+
+/* Choose the smoothness indicators (hjw_scheme; HJW_WENO_L until set).  Takes effect
+ * from the next step; HJW_EINVAL for an unknown scheme. */
+hjw_status hjw_set_scheme(hjw_grid *g, int scheme);
 
 /* Copy phi0 (FP64, nx*ny values, host or device memory) into the grid; t := 0,
  * steps := 0, the failed state is cleared.  Synchronous. */
@@ -176,6 +187,8 @@ typedef struct {
     double params[4];  /* Hamiltonian parameters                                  */
     double t_final;    /* solve from t = 0 to t_final                             */
     double cfl;        /* CFL number, as for hjw_step_to                          */
+    int scheme;        /* hjw_scheme                                              */
+    int reserved;      /* 0                                                       */
 } hjw_request;
 
 typedef struct {

@@ -8,6 +8,9 @@ the benchmark may import it.  It shares no code with the GPU library.
 Parity status of each routine (what pins it lives in ``tests/test_oracle_*``):
   weno_l_minus / weno_l_plus   pinned: brute force (Lagrange cubics + quadrature),
                                exactness on cubics, convergence orders
+  weno_jp_minus / weno_jp_plus the comparison scheme (WENO-JP); pinned: its form equals
+                               the weighted candidates, fifth-order rows with linear
+                               weights, the WENO-JP columns of Tables 1-4
   arc_length                   pinned: adaptive quadrature, closed special cases
   derivatives                  pinned: brute force on 8-point grids, symmetries
   hamiltonian / lax_friedrichs pinned: consistency H_hat(u,u) = H(u), monotonicity
@@ -31,6 +34,7 @@ _LIB = os.path.join(_HERE, "libhjw_oracle.so")
 
 BC_PERIODIC, BC_EXTRAP = 0, 1
 H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM = 0, 1, 2, 3
+WENO_L, WENO_JP = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -47,7 +51,8 @@ def build(force: bool = True) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
                 ("ham", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
-                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("hp", ctypes.c_double * 4)]
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("hp", ctypes.c_double * 4),
+                ("scheme", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -70,6 +75,10 @@ def _load():
         lib.orc_weno_l_minus.argtypes = [dp, ctypes.c_double, dp, dp]
         lib.orc_weno_l_plus.restype = ctypes.c_double
         lib.orc_weno_l_plus.argtypes = [dp, ctypes.c_double, dp, dp]
+        lib.orc_weno_jp_minus.restype = ctypes.c_double
+        lib.orc_weno_jp_minus.argtypes = [dp, ctypes.c_double, dp, dp]
+        lib.orc_weno_jp_plus.restype = ctypes.c_double
+        lib.orc_weno_jp_plus.argtypes = [dp, ctypes.c_double, dp, dp]
         lib.orc_candidates.restype = None
         lib.orc_candidates.argtypes = [dp, dp]
         lib.orc_arc_length.restype = ctypes.c_double
@@ -102,12 +111,13 @@ class Problem:
 
     ``shape`` is (nx,) or (ny, nx) (row-major, x fastest); ``h`` is (dx,) or (dx, dy);
     ``bc`` is one code for all axes or a pair (bc_x, bc_y); ``params`` are the
-    Hamiltonian parameters (see ``hamiltonian``)."""
+    Hamiltonian parameters (see ``hamiltonian``); ``scheme`` is WENO_L or WENO_JP."""
     shape: tuple
     h: tuple
     ham: int
     params: tuple
     bc: object = BC_PERIODIC
+    scheme: int = WENO_L
     _c: _Problem = field(init=False, repr=False)
 
     def __post_init__(self):
@@ -122,6 +132,7 @@ class Problem:
         bcs = self.bc if isinstance(self.bc, (tuple, list)) else (self.bc, self.bc)
         p.bc_x, p.bc_y = int(bcs[0]), int(bcs[1])
         p.ham = int(self.ham)
+        p.scheme = int(self.scheme)
         hp = list(self.params) + [0.0] * (4 - len(self.params))
         for k in range(4):
             p.hp[k] = float(hp[k])
@@ -176,6 +187,28 @@ def weno_l_plus(g, dx):
     omega = np.zeros(3)
     u = lib.orc_weno_l_plus(_dptr(g), float(dx), _dptr(beta), _dptr(omega))
     return u, beta, omega
+
+
+def weno_jp_minus(f, dx):
+    """WENO-JP phi_x^- at x_i from phi_{i-3..i+2}; returns (u, IS[3], omega[3])."""
+    lib = _load()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.shape == (6,)
+    ind = np.zeros(3)
+    omega = np.zeros(3)
+    u = lib.orc_weno_jp_minus(_dptr(f), float(dx), _dptr(ind), _dptr(omega))
+    return u, ind, omega
+
+
+def weno_jp_plus(g, dx):
+    """WENO-JP phi_x^+ at x_i from phi_{i-2..i+3}; returns (u, IS[3], omega[3])."""
+    lib = _load()
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape == (6,)
+    ind = np.zeros(3)
+    omega = np.zeros(3)
+    u = lib.orc_weno_jp_plus(_dptr(g), float(dx), _dptr(ind), _dptr(omega))
+    return u, ind, omega
 
 
 def arc_length(b, c, x_lo, x_hi):

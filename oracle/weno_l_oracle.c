@@ -13,6 +13,8 @@
  *   arc_length            Step 4, eq. (length) and the primitive I[b,c,z]
  *   weno_l_minus          Steps 2-4, eqs. (WLOC1) and (newbeta), linear weights of Step 3
  *   weno_l_plus           Step 2, "symmetric procedure with respect to x_i"
+ *   weno_jp_minus/plus    the comparison scheme of Section 3 (WENO-JP), from its own
+ *                         publication (Jiang and Peng, SIAM J. Sci. Comput. 21, 2000)
  *   hamiltonian           the test problems of Section 3 (Examples 3.1-3.4, 3.6, 3.12)
  *   dissipation           eq. (LF): alpha = max |H_1| (global box reading, see below)
  *   lax_friedrichs        eq. (LF)
@@ -45,6 +47,7 @@
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1 };
 enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3 };
+enum { ORC_SCHEME_WENO_L = 0, ORC_SCHEME_WENO_JP = 1 };
 
 typedef struct {
     int32_t dim;       /* 1 or 2 */
@@ -56,6 +59,8 @@ typedef struct {
     double dx;
     double dy;
     double hp[4];      /* Hamiltonian parameters, see hamiltonian() */
+    int32_t scheme;    /* ORC_SCHEME_*: WENO-L (the paper's) or WENO-JP (its comparison) */
+    int32_t pad;
 } orc_problem;
 
 typedef struct {
@@ -187,6 +192,55 @@ double orc_weno_l_plus(const double g[6], double dx, double *beta_out, double *o
 }
 
 /* ---------------------------------------------------------------------------
+ * The comparison scheme WENO-JP, written in its authors' form: with
+ * v_j = Delta^+ phi_j / dx and the second differences
+ *   a, b, c, d = Delta^- Delta^+ phi_{i-2}, ..., phi_{i+1}, divided by dx,
+ *   phi_{x,i}^- = (-v_{i-2} + 7 v_{i-1} + 7 v_i - v_{i+1}) / 12 - Phi(a, b, c, d),
+ *   Phi = omega_0 (a - 2b + c) / 3 + (omega_2 - 1/2) (b - 2c + d) / 6,
+ *   IS_0 = 13 (a-b)^2 + 3 (a-3b)^2,  IS_1 = 13 (b-c)^2 + 3 (b+c)^2,
+ *   IS_2 = 13 (c-d)^2 + 3 (3c-d)^2,
+ *   alpha_k = d_k / (eps + IS_k)^2, omega_k = alpha_k / sum alpha,
+ * with the linear weights d = (1, 6, 3)/10 and eps = 1e-6 as in WENO-L.
+ * f[0..5] = phi_{i-3}, ..., phi_{i+2}; optionally returns IS_k and omega_k.
+ * ------------------------------------------------------------------------- */
+double orc_weno_jp_minus(const double f[6], double dx, double *is_out, double *omega_out)
+{
+    static const double d[3] = {1.0 / 10.0, 6.0 / 10.0, 3.0 / 10.0};
+    double v[5], is[3], alpha[3], omega[3];
+    int k;
+    for (k = 0; k < 5; ++k)
+        v[k] = (f[k + 1] - f[k]) / dx; /* Delta^+ phi_{i-3+k} / dx */
+    const double a = v[1] - v[0], b = v[2] - v[1], c = v[3] - v[2], e = v[4] - v[3];
+    is[0] = 13.0 * (a - b) * (a - b) + 3.0 * (a - 3.0 * b) * (a - 3.0 * b);
+    is[1] = 13.0 * (b - c) * (b - c) + 3.0 * (b + c) * (b + c);
+    is[2] = 13.0 * (c - e) * (c - e) + 3.0 * (3.0 * c - e) * (3.0 * c - e);
+    double sum = 0.0;
+    for (k = 0; k < 3; ++k) {
+        alpha[k] = d[k] / ((ORC_EPS + is[k]) * (ORC_EPS + is[k]));
+        sum += alpha[k];
+    }
+    for (k = 0; k < 3; ++k)
+        omega[k] = alpha[k] / sum;
+    const double phi_weno = omega[0] * (a - 2.0 * b + c) / 3.0
+                            + (omega[2] - 0.5) * (b - 2.0 * c + e) / 6.0;
+    const double u = (-v[1] + 7.0 * v[2] + 7.0 * v[3] - v[4]) / 12.0 - phi_weno;
+    if (is_out)
+        for (k = 0; k < 3; ++k) is_out[k] = is[k];
+    if (omega_out)
+        for (k = 0; k < 3; ++k) omega_out[k] = omega[k];
+    return u;
+}
+
+/* phi_{x,i}^+ of WENO-JP by the same reflection as weno_l_plus. */
+double orc_weno_jp_plus(const double g[6], double dx, double *is_out, double *omega_out)
+{
+    double r[6];
+    for (int k = 0; k < 6; ++k)
+        r[k] = g[5 - k];
+    return -orc_weno_jp_minus(r, dx, is_out, omega_out);
+}
+
+/* ---------------------------------------------------------------------------
  * Ghost values: three per side.  periodic wraps; extrapolation continues the
  * line through the two end points.
  * ------------------------------------------------------------------------- */
@@ -207,13 +261,18 @@ static void fill_line(const double *src, int64_t stride, int64_t n, int bc, doub
     }
 }
 
-static void line_derivatives(const double *ext, int64_t n, double h, double *dm, int64_t sm,
-                             double *dp, int64_t sp)
+static void line_derivatives(const double *ext, int64_t n, double h, int scheme, double *dm,
+                             int64_t sm, double *dp, int64_t sp)
 {
     for (int64_t i = 0; i < n; ++i) {
         /* ext[i+3] is node i: window phi_{i-3..i+2} starts at ext[i], phi_{i-2..i+3} at ext[i+1] */
-        dm[i * sm] = orc_weno_l_minus(ext + i, h, NULL, NULL);
-        dp[i * sp] = orc_weno_l_plus(ext + i + 1, h, NULL, NULL);
+        if (scheme == ORC_SCHEME_WENO_JP) {
+            dm[i * sm] = orc_weno_jp_minus(ext + i, h, NULL, NULL);
+            dp[i * sp] = orc_weno_jp_plus(ext + i + 1, h, NULL, NULL);
+        } else {
+            dm[i * sm] = orc_weno_l_minus(ext + i, h, NULL, NULL);
+            dp[i * sp] = orc_weno_l_plus(ext + i + 1, h, NULL, NULL);
+        }
     }
 }
 
@@ -232,7 +291,7 @@ int orc_derivatives(const orc_problem *p, const double *phi, double *um, double 
     for (j = 0; j < ny; ++j) {
         double *ext = (double *)malloc((size_t)(nx + 6) * sizeof(double));
         fill_line(phi + j * nx, 1, nx, p->bc_x, ext);
-        line_derivatives(ext, nx, p->dx, um + j * nx, 1, up + j * nx, 1);
+        line_derivatives(ext, nx, p->dx, p->scheme, um + j * nx, 1, up + j * nx, 1);
         free(ext);
     }
     if (p->dim == 2) {
@@ -241,7 +300,7 @@ int orc_derivatives(const orc_problem *p, const double *phi, double *um, double 
         for (i = 0; i < nx; ++i) {
             double *ext = (double *)malloc((size_t)(ny + 6) * sizeof(double));
             fill_line(phi + i, nx, ny, p->bc_y, ext);
-            line_derivatives(ext, ny, p->dy, vm + i, nx, vp + i, nx);
+            line_derivatives(ext, ny, p->dy, p->scheme, vm + i, nx, vp + i, nx);
             free(ext);
         }
     }

@@ -72,6 +72,7 @@ struct hjw_grid {
     int tile_rows = 16;  // 2-D tile height (16 or 32)
     int seg_opt = 0;     // nodes per thread in the 2-D sweeps: 0 automatic, 4 or 8
     int plan_opt = 0;    // step plan: 0 automatic, 1 in every workgroup, 2 own launch
+    int scheme = HJW_WENO_L;
 
     // host mirror
     DevState* pinned = nullptr;  // pinned host copy of the device state
@@ -151,8 +152,9 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     a.ihy = P(1.0 / g->dy);
     a.ihxT = T(1.0 / g->dx);
     a.ihyT = T(1.0 / g->dy);
-    a.epsx = T(4.0 * kEps / (g->dx * g->dx));
-    a.epsy = T(4.0 * kEps / (g->dy * g->dy));
+    a.epsx = T(weight_eps(g->scheme, g->dx));
+    a.epsy = T(weight_eps(g->scheme, g->dy));
+    a.scheme = g->scheme;
     a.ham = g->ham;
     for (int k = 0; k < 4; ++k) {
         a.hpT[k] = T(g->hp[k]);
@@ -442,6 +444,17 @@ hjw_status hjw_bind(hjw_grid* g, void* ws, size_t bytes, void* stream) {
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(g->stream));
     g->last = DevState{};
+    return HJW_OK;
+}
+
+hjw_status hjw_set_scheme(hjw_grid* g, int scheme) {
+    if (!g) return fail(HJW_EINVAL, "grid is NULL");
+    if (scheme != HJW_WENO_L && scheme != HJW_WENO_JP)
+        return fail(HJW_EINVAL, "unknown scheme %d", scheme);
+    if (scheme != g->scheme) {
+        g->scheme = scheme;
+        drop_graph(g);   // graphs hold the stage arguments
+    }
     return HJW_OK;
 }
 

@@ -23,6 +23,7 @@ namespace {
 
 int g_tile_rows = 32;  // 2-D tile height being emulated (32 or 16)
 int g_segment = 8;     // nodes per thread in the 2-D sweeps (8, or 4 with 16-row tiles)
+int g_scheme = 0;      // kSchemeL or kSchemeJP
 constexpr size_t kGuard = 4096;
 
 template <typename X>
@@ -91,8 +92,9 @@ struct Emu {
         a.ihy = P(1.0 / pr.dy);
         a.ihxT = T(1.0 / pr.dx);
         a.ihyT = T(1.0 / pr.dy);
-        a.epsx = T(4.0 * kEps / (pr.dx * pr.dx));
-        a.epsy = T(4.0 * kEps / (pr.dy * pr.dy));
+        a.epsx = T(weight_eps(g_scheme, pr.dx));
+        a.epsy = T(weight_eps(g_scheme, pr.dy));
+        a.scheme = g_scheme;
         a.ham = pr.ham;
         for (int k = 0; k < 4; ++k) a.hpT[k] = T(pr.hp[k]);
         a.nbx = nbx;
@@ -285,6 +287,13 @@ int hjw_emu_set_tile_rows(int rows) {
     if (rows != 16 && rows != 32) return -1;
     if (rows == 32 && g_segment != 8) return -1;
     g_tile_rows = rows;
+    return 0;
+}
+
+// Scheme of the emulated kernels: 0 WENO-L, 1 WENO-JP.
+int hjw_emu_set_scheme(int scheme) {
+    if (scheme != kSchemeL && scheme != kSchemeJP) return -1;
+    g_scheme = scheme;
     return 0;
 }
 

@@ -205,6 +205,8 @@ hjw_status validate(const hjw_request& r) {
     }
     if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_NORM)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", r.ham);
+    if (r.scheme != HJW_WENO_L && r.scheme != HJW_WENO_JP)
+        return fail(HJW_EINVAL, "unknown scheme %d", r.scheme);
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(r.params[k])) return fail(HJW_EINVAL, "non-finite parameter");
     if (r.ham == HJW_H_NORM && r.params[1] < 0.0) return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
@@ -287,8 +289,9 @@ StageArgs<T, P> request_args(const hjw_server* s, const Req& q) {
     a.ihy = P(1.0 / dy);
     a.ihxT = T(1.0 / dx);
     a.ihyT = T(1.0 / dy);
-    a.epsx = T(4.0 * kEps / (dx * dx));
-    a.epsy = T(4.0 * kEps / (dy * dy));
+    a.epsx = T(weight_eps(r.scheme, dx));
+    a.epsy = T(weight_eps(r.scheme, dy));
+    a.scheme = r.scheme;
     a.ham = r.ham;
     for (int k = 0; k < 4; ++k) {
         a.hpT[k] = T(r.params[k]);

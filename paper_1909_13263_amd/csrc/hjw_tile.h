@@ -56,6 +56,18 @@ constexpr int kStageDeriv = 3;  // derivatives only (u-, u+, v-, v+ as FP64)
 
 constexpr double kEps = 1.0e-6;  // epsilon of eq. (WLOC1)
 
+// Schemes: WENO-L (the paper's arc-length indicators) and WENO-JP (the comparison
+// scheme of Section 3: Jiang and Peng's indicators, same candidates and weights).
+constexpr int kSchemeL = 0;
+constexpr int kSchemeJP = 1;
+
+// The additive constant of t_k = (eps' + X_k)^2 in the weights, per scheme: WENO-L
+// works with X = (2M)^2 = 4 beta / h^2, so eps' = 4 eps / h^2; WENO-JP's indicators are
+// used as defined, so eps' = eps.
+inline double weight_eps(int scheme, double h) {
+    return scheme == kSchemeJP ? kEps : 4.0 * kEps / (h * h);
+}
+
 // Tile shapes: 64 x TY nodes per workgroup in 2-D (TY = 16 or 32), each thread
 // marching a segment of S nodes along a row or a column (S = 8, or S = 4 for twice
 // the threads on grids too small to fill the GPU) and then finishing S/2 nodes;
@@ -140,7 +152,7 @@ __host__ __device__ inline double mean2sq_series(double sg, double dl, double q4
     const double inner =
         (2.0 / 3.0) + g2 * (0.4 * (s2 - 1.0) + g2 * ((2.0 / 7.0) * (s2 * (s2 - 6.0) + 2.0)));
     const double X = 1.0 + g2 * inner;
-    return (q4 * X) * X;
+    return mul_rn(q4 * X, X);   // rounded alone: the weights add eps to it on every path
 }
 __host__ __device__ inline float mean2sq_series(float sg, float dl, float q4, float& xx) {
     const float g = dl * rcp_t(q4);
@@ -148,7 +160,7 @@ __host__ __device__ inline float mean2sq_series(float sg, float dl, float q4, fl
     const float g2 = g * g;
     const float inner = (2.0f / 3.0f) + g2 * (0.4f * (sg * sg - 1.0f));
     const float X = 1.0f + g2 * inner;
-    return (q4 * X) * X;
+    return mul_rn(q4 * X, X);
 }
 
 // Antiderivative of sqrt(1+s^2): (s sqrt(1+s^2) + asinh s) / 2.
@@ -183,7 +195,10 @@ __host__ __device__ inline float wdiv<float>(float num, float den) {
 
 // Squares of the doubled means for the three pairs of one cell: (c0, b1), (c0, c1),
 // (f0, c1).  A pair whose relative half-gap is not small takes the antiderivative
-// instead; the wave takes that branch only when one of its lanes needs it.
+// instead; the wave takes that branch only when one of its lanes needs it.  The
+// squares are rounded on their own (mul_rn), so that a lane's value does not depend
+// on whether its wave took the branch (a product fused into the weights' sums on one
+// path only would round differently).
 template <typename T>
 __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA2, T& MB2, T& MC2) {
     const T tau2 = SeriesCfg<T>::tau2;
@@ -200,17 +215,32 @@ __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA2, T& MB
         const T Pc0 = prim(c0), Pb1 = prim(b1), Pc1 = prim(c1), Pf0 = prim(f0);
         if (xA >= tau2) {
             const T M = wdiv(T(2) * (Pb1 - Pc0), dA);
-            MA2 = M * M;
+            MA2 = mul_rn(M, M);
         }
         if (xB >= tau2) {
             const T M = wdiv(T(2) * (Pc1 - Pc0), dB);
-            MB2 = M * M;
+            MB2 = mul_rn(M, M);
         }
         if (xC >= tau2) {
             const T M = wdiv(T(2) * (Pc1 - Pf0), dC);
-            MC2 = M * M;
+            MC2 = mul_rn(M, M);
         }
     }
+}
+
+// WENO-JP indicators of the three sub-stencils of one cell from the second differences
+// (divided by h) e1..e4 = Delta^- Delta^+ phi_{i-2..i+1} / h:
+//   IS_A = 13 (e1-e2)^2 + 3 (e1-3 e2)^2, IS_B = 13 (e2-e3)^2 + 3 (e2+e3)^2,
+//   IS_C = 13 (e3-e4)^2 + 3 (3 e3-e4)^2;
+// as for WENO-L, the same three serve phi^-_i and, reversed, phi^+_{i-1}.
+template <typename T>
+__host__ __device__ inline void jp_indicators(T e1, T e2, T e3, T e4, T& IA, T& IB, T& IC) {
+    const T a0 = e1 - e2, a1 = e1 - T(3) * e2;
+    const T b0 = e2 - e3, b1 = e2 + e3;
+    const T c0 = e3 - e4, c1 = T(3) * e3 - e4;
+    IA = T(13) * (a0 * a0) + T(3) * (a1 * a1);
+    IB = T(13) * (b0 * b0) + T(3) * (b1 * b1);
+    IC = T(13) * (c0 * c0) + T(3) * (c1 * c1);
 }
 
 // Products of the weight denominators: with t_k = (eps/h^2 + M_k^2)^2 (up to a
@@ -255,7 +285,7 @@ __host__ __device__ inline void weight_products(float MA2, float MB2, float MC2,
 //   q1 = c + (e2 + 2 e3)/6 for phi^- at x_i, and mirrored for phi^+ at x_{i-1}:
 //   qp1 = c - (e3 + 2 e2)/6, qp0 - qp1 = -D3b/3, qp2 - qp1 = -D3a/6.
 // So phi^- = q1 + (w0 (q0-q1) + w2 (q2-q1)) / (w0 + w1 + w2), and likewise phi^+.
-template <typename T, typename P, int S>
+template <typename T, typename P, int S, int SCHEME>
 __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T eps4, T* um,
                                       T* up) {
     // The quotients are rounded on their own: fused into the differences that follow,
@@ -265,20 +295,26 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
     for (int k = 0; k < S + 5; ++k)
         v[k] = T(mul_rn(line[(k + 1) * stride] - line[k * stride], ihP));
     T e1 = v[1] - v[0], e2 = v[2] - v[1], e3 = v[3] - v[2];
-    T c0 = e2 * ih;
+    // The end values are rounded on their own too: C_i is carried to the next cell, and a
+    // product fused into a sum in one iteration but not in another would make a node's
+    // value depend on where its segment starts.
+    T c0 = mul_rn(e2, ih);
 #pragma unroll
     for (int it = 0; it <= S; ++it) {
         const T c = v[it + 2];
         const T e4 = v[it + 4] - v[it + 3];
         const T B1 = T(2) * e2 - e1;          // h B_i
         const T F0 = T(2) * e3 - e4;          // h F_{i-1}
-        const T c1 = e3 * ih;                 // C_i
-        const T b1 = B1 * ih;                 // B_i
-        const T f0 = F0 * ih;                 // F_{i-1}
-        T MA2, MB2, MC2;
-        cell_means(c0, b1, c1, f0, MA2, MB2, MC2);
+        const T c1 = mul_rn(e3, ih);          // C_i
+        const T b1 = mul_rn(B1, ih);          // B_i
+        const T f0 = mul_rn(F0, ih);          // F_{i-1}
+        T XA, XB, XC;   // squared doubled means (WENO-L) or indicators (WENO-JP)
+        if (SCHEME == kSchemeJP)
+            jp_indicators(e1, e2, e3, e4, XA, XB, XC);
+        else
+            cell_means(c0, b1, c1, f0, XA, XB, XC);
         T pAB, pAC, pBC;
-        weight_products(MA2, MB2, MC2, eps4, pAB, pAC, pBC);
+        weight_products(XA, XB, XC, eps4, pAB, pAC, pBC);
         const T D3a = B1 - e3;                // a - 3b + 3c - d
         const T D3b = F0 - e2;                // b - 3c + 3d - e
         // numerators and denominators below are six times those of the weighted sums
@@ -409,7 +445,7 @@ struct StageArgs {
     int bcx, bcy;
     P ihx, ihy;       // 1/dx, 1/dy in the storage precision
     T ihxT, ihyT;
-    T epsx, epsy;     // 4 eps/dx^2, 4 eps/dy^2 (the weights use doubled means)
+    T epsx, epsy;     // weight_eps(scheme, dx), weight_eps(scheme, dy)
     int ham;
     T hpT[4];
     double hpD[4];    // the same parameters in FP64 (dissipation, time step)
@@ -418,6 +454,7 @@ struct StageArgs {
     int remap;        // nonzero: spread neighbouring tiles over one XCD
     int dim;
     int plan_ready;   // nonzero: the step plan was published by its own launch
+    int scheme;       // kSchemeL or kSchemeJP
 };
 
 // Stage input at a node inside the grid.
@@ -659,7 +696,13 @@ struct Tile {
         const int row = t % TY;
         const int seg = t / TY;
         T um[SX], up[SX];
-        sweep<T, P, SX>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT, a.epsx, um, up);
+        // the scheme is uniform over the launch: one branch around the whole march
+        if (a.scheme == kSchemeJP)
+            sweep<T, P, SX, kSchemeJP>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT, a.epsx,
+                                       um, up);
+        else
+            sweep<T, P, SX, kSchemeL>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT, a.epsx,
+                                      um, up);
 #pragma unroll
         for (int k = 0; k < SX; ++k) {
             uL[row * UW + seg * SX + k] = um[k];
@@ -672,7 +715,12 @@ struct Tile {
                                             T* vp) {
         const int col = t % TX;
         const int seg = t / TX;
-        sweep<T, P, SY>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy, vm, vp);
+        if (a.scheme == kSchemeJP)
+            sweep<T, P, SY, kSchemeJP>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy,
+                                       vm, vp);
+        else
+            sweep<T, P, SY, kSchemeL>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy,
+                                      vm, vp);
     }
 
     // The finish is shared by all threads: a column thread keeps the first SY/2 of its
@@ -736,7 +784,10 @@ struct Tile1D {
     __host__ __device__ static void sweep_x(int tid, const StageArgs<T, P>& a, const P* phiL,
                                             T* uL) {
         T um[S], up[S];
-        sweep<T, P, S>(phiL + tid * S, 1, a.ihx, a.ihxT, a.epsx, um, up);
+        if (a.scheme == kSchemeJP)
+            sweep<T, P, S, kSchemeJP>(phiL + tid * S, 1, a.ihx, a.ihxT, a.epsx, um, up);
+        else
+            sweep<T, P, S, kSchemeL>(phiL + tid * S, 1, a.ihx, a.ihxT, a.epsx, um, up);
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             uL[tid * S + k] = um[k];

@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_EXTRAP = 0, 1
 FP64, FP32_MIXED, FP32 = 0, 1, 2
 H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM = 0, 1, 2, 3
+WENO_L, WENO_JP = 0, 1
 OPT_USE_GRAPH = 0
 OPT_KERNEL_EVENTS = 1
 OPT_TILE_ROWS = 2
@@ -45,7 +46,7 @@ class _Request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64 * 2), ("lo", ctypes.c_double * 2),
                 ("hi", ctypes.c_double * 2), ("bc", ctypes.c_int * 2), ("ham", ctypes.c_int),
                 ("params", ctypes.c_double * 4), ("t_final", ctypes.c_double),
-                ("cfl", ctypes.c_double)]
+                ("cfl", ctypes.c_double), ("scheme", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -84,6 +85,7 @@ def lib():
             "hjw_workspace_bytes": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t)]),
             "hjw_bind": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
             "hjw_set_hamiltonian": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.c_int]),
+            "hjw_set_scheme": (ctypes.c_int, [vp, ctypes.c_int]),
             "hjw_set_phi": (ctypes.c_int, [vp, vp, ctypes.c_int]),
             "hjw_step_to": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, i64,
                                            ctypes.POINTER(_Info)]),
@@ -169,6 +171,10 @@ class Grid:
         p = (ctypes.c_double * 4)(*([float(v) for v in params] + [0.0] * (4 - len(params))))
         _check(lib().hjw_set_hamiltonian(self._h, int(kind), p, len(params)))
 
+    def set_scheme(self, scheme):
+        """WENO_L (default) or WENO_JP."""
+        _check(lib().hjw_set_scheme(self._h, int(scheme)))
+
     def set_phi(self, phi):
         import torch
         if isinstance(phi, torch.Tensor) and phi.is_cuda:
@@ -242,14 +248,16 @@ class Grid:
             pass
 
 
-def grid_for(problem, prec=FP64, **kw) -> Grid:
-    """A Grid for a workloads.Problem, with its Hamiltonian set."""
+def grid_for(problem, prec=FP64, scheme=WENO_L, **kw) -> Grid:
+    """A Grid for a workloads.Problem, with its Hamiltonian (and scheme) set."""
     g = Grid(problem.shape, problem.lo, problem.hi, problem.bc, prec, **kw)
     g.set_hamiltonian(problem.ham, problem.params)
+    if scheme != WENO_L:
+        g.set_scheme(scheme)
     return g
 
 
-def _request(problem, shape=None) -> _Request:
+def _request(problem, scheme=WENO_L) -> _Request:
     """The C request record of a 2-D workloads.Problem."""
     if len(problem.shape) != 2:
         raise ValueError("the server takes 2-D problems")
@@ -267,6 +275,7 @@ def _request(problem, shape=None) -> _Request:
         r.params[k] = params[k]
     r.t_final = float(problem.t_final)
     r.cfl = float(problem.cfl)
+    r.scheme = int(scheme)
     return r
 
 
@@ -316,8 +325,8 @@ class Server:
         _check(lib().hjw_server_footprint(int(prec), ctypes.byref(r), ctypes.byref(out)))
         return int(out.value)
 
-    def submit(self, problem, phi0=None) -> int:
-        r = _request(problem)
+    def submit(self, problem, phi0=None, scheme=WENO_L) -> int:
+        r = _request(problem, scheme)
         a = problem.phi0() if phi0 is None else phi0
         a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
         if a.shape != tuple(problem.shape):

@@ -25,6 +25,8 @@ def lib():
         L.hjw_emu_set_tile_rows.argtypes = [ctypes.c_int]
         L.hjw_emu_set_segment.restype = ctypes.c_int
         L.hjw_emu_set_segment.argtypes = [ctypes.c_int]
+        L.hjw_emu_set_scheme.restype = ctypes.c_int
+        L.hjw_emu_set_scheme.argtypes = [ctypes.c_int]
         L.hjw_emu_step.restype = ctypes.c_int
         L.hjw_emu_step.argtypes = [ctypes.c_int, i64, i64, d, d, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, vp, vp, d, d, d, vp]
@@ -34,6 +36,11 @@ def lib():
 
 def set_tile_rows(rows):
     assert lib().hjw_emu_set_tile_rows(int(rows)) == 0
+
+
+def set_scheme(scheme):
+    """0 WENO-L, 1 WENO-JP for the emulated kernels."""
+    assert lib().hjw_emu_set_scheme(int(scheme)) == 0
 
 
 def set_tile(rows, segment):

@@ -93,6 +93,8 @@ def test_segment_and_tile_options_are_validated():
     assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 0) == hjw.OK
     assert L.hjw_set_option(h32, hjw.OPT_TILE_ROWS, 32) == hjw.OK
     assert L.hjw_set_option(h32, hjw.OPT_SEGMENT, 4) == hjw.EINVAL
+    assert L.hjw_set_scheme(h32, 2) == hjw.EINVAL
+    assert L.hjw_set_scheme(h32, hjw.WENO_JP) == hjw.OK
     assert L.hjw_set_option(h32, hjw.OPT_PLAN, 3) == hjw.EINVAL
     assert L.hjw_set_option(h32, hjw.OPT_PLAN, 2) == hjw.OK
     L.hjw_grid_destroy(h64)
@@ -129,6 +131,7 @@ def test_server_footprint(prec, per_cell, n):
     ("ham", 11, "Hamiltonian"),
     ("t_final", -1.0, "t_final"),
     ("cfl", 0.0, "cfl"),
+    ("scheme", 5, "unknown scheme"),
 ])
 def test_server_footprint_validates(field, value, msg):
     from paper_1909_13263_amd import workloads as W

@@ -82,3 +82,40 @@ def test_emulated_transpose_is_bitwise():
         _, b, _ = EM.rk3_step(np.ascontiguousarray(phi.T), pr.spacing, pr.ham, pr.params, 0.0,
                               1.0, 0.5, 0, prec)
         assert np.array_equal(a, b.T)
+
+
+# --------------------------------------------------------------------------- WENO-JP
+@pytest.fixture
+def weno_jp():
+    EM.set_scheme(O.WENO_JP)
+    yield
+    EM.set_scheme(O.WENO_L)
+
+
+@pytest.mark.parametrize("shape", [(37,), (1030,), (8, 8), (33, 65), (100, 200), (135, 260)])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_jp_derivatives_match_oracle(shape, bc, prec, weno_jp):
+    """The comparison scheme's indicators in the same tile code: against the oracle's
+    WENO-JP, element by element."""
+    rng = np.random.default_rng(len(shape) * 1000 + sum(shape) + 7)
+    phi = W.random_smooth_periodic(shape, seed=sum(shape)) + 0.05 * rng.normal(size=shape)
+    h = tuple(0.05 + 0.01 * a for a in range(len(shape)))
+    ref = O.derivatives(O.Problem(shape, h, O.H_LINEAR, (1.0, 0.0), bc, scheme=O.WENO_JP), phi)
+    got = EM.derivatives(phi, h, bc, prec)
+    for g, r in zip(got, ref):
+        assert np.abs(g - r).max() <= TOL[prec] * np.abs(r).max()
+
+
+@pytest.mark.parametrize("case", [0, 3, 5, 7])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_emulated_jp_rk3_step_matches_oracle(case, prec, weno_jp):
+    pr = _cases()[case]
+    phi = pr.phi0()
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc, scheme=O.WENO_JP)
+    ref, info = O.rk3_step(prob, phi, 0.0, pr.t_final, 0.5)
+    rc, got, ei = EM.rk3_step(phi, pr.spacing, pr.ham, pr.params, 0.0, pr.t_final, 0.5, pr.bc,
+                              prec)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    assert np.abs(got - ref).max() <= {0: 1e-14, 1: 1e-7}[prec] * np.abs(ref).max()

@@ -63,3 +63,18 @@ def test_fp32_error_bounds_at_full_size(name, make, bounds):
         print(f"{name} prec={prec} steps={pinfo.steps}/{info.steps} linf={linf:.3e} l1={l1:.3e}")
         assert abs(pinfo.steps - info.steps) <= 1
         assert linf <= linf_max and l1 <= l1_max
+
+
+def test_burgers_1024_fp64_whole_solve_matches_oracle():
+    """The 1024^2 Burgers configuration solved to t = 0.5/pi^2 (215 steps) in FP64 on the
+    GPU and by the FP64 oracle on the host cores: every node within 1e-12 of max|phi|."""
+    import oracle as O
+    pr = W.burgers2d(1024, 0.5 / math.pi**2)
+    phi0 = pr.phi0()
+    ref, info = O.step_to(O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc), phi0,
+                          pr.t_final, pr.cfl)
+    got, ginfo = _solve(pr, FP64)
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    print(f"burgers 1024^2 FP64 whole solve: steps {ginfo.steps}/{info.steps} rel {err:.3e}")
+    assert ginfo.steps == info.steps
+    assert err <= 1e-12

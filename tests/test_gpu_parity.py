@@ -324,3 +324,74 @@ def test_time_kernels_contract():
     assert e.value.code == hjw.ESTATE
     g.set_phi(pr.phi0())
     g.step_to(0.001, 0.5)
+
+
+# --------------------------------------------------------------------------- WENO-JP
+JP_SHAPES = [(37,), (1030,), (8, 8), (33, 65), (100, 200), (135, 260), (256, 256)]
+
+
+@pytest.mark.parametrize("shape", JP_SHAPES)
+@pytest.mark.parametrize("bc", [hjw.BC_PERIODIC, hjw.BC_EXTRAP])
+@pytest.mark.parametrize("prec", [FP64, MIXED, FP32])
+def test_jp_derivatives_match_oracle(shape, bc, prec):
+    """The comparison scheme (WENO-JP indicators): derivatives against the oracle's WENO-JP."""
+    phi = _field(shape, seed=sum(shape) + 11 * bc)
+    lo = [0.0] * len(shape)
+    hi = [0.05 * n for n in shape[::-1]]
+    g = hjw.Grid(shape, lo, hi, bc, prec)
+    g.set_scheme(hjw.WENO_JP)
+    g.set_phi(phi)
+    got = [t.cpu().numpy() for t in g.derivatives()]
+    h = tuple((hi[a] - lo[a]) / shape[::-1][a] for a in range(len(shape)))
+    ref = O.derivatives(O.Problem(shape, h, O.H_LINEAR, (1.0, 0.0), bc, scheme=O.WENO_JP), phi)
+    for a, r in zip(got, ref):
+        assert np.abs(a - r).max() <= DERIV_TOL[prec] * np.abs(r).max()
+
+
+@pytest.mark.parametrize("make", [lambda: W.burgers2d(128, 1.5 / math.pi**2),
+                                  lambda: W.negcos2d(160, 0.5 / math.pi**2),
+                                  lambda: W.levelset2d(120, 0.05)])
+def test_jp_whole_solves_match_oracle(make):
+    """WENO-JP whole solves: FP64 within 1e-12 of the oracle, the FP32 stencil within 2e-6."""
+    pr = make()
+    ref, info = O.step_to(O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc,
+                                    scheme=O.WENO_JP), pr.phi0(), pr.t_final, 0.5)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 2e-6)]:
+        g = hjw.grid_for(pr, prec, scheme=hjw.WENO_JP)
+        g.set_phi(pr.phi0())
+        gi = g.step_to(pr.t_final, 0.5)
+        assert abs(gi.steps - info.steps) <= (0 if prec == FP64 else 1)
+        err = _rel(g.get_phi(), ref)
+        print(f"JP {pr.name} {pr.shape} prec={prec} rel={err:.3e}")
+        assert err <= tol
+
+
+def test_jp_full_size_steps_match_oracle():
+    """WENO-JP at the 1024^2 benchmark shape: three whole steps against the oracle."""
+    pr = W.burgers2d(1024)
+    ref, _ = O.step_to(O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc,
+                                 scheme=O.WENO_JP), pr.phi0(), pr.t_final, 0.5, max_steps=3)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 1e-6)]:
+        g = hjw.grid_for(pr, prec, scheme=hjw.WENO_JP)
+        g.set_phi(pr.phi0())
+        g.step_to(pr.t_final, 0.5, max_steps=3)
+        assert _rel(g.get_phi(), ref) <= tol
+        g.close()
+
+
+def test_scheme_switch_applies_to_the_next_step():
+    """hjw_set_scheme between steps: WENO-L then WENO-JP equals the oracle doing the same."""
+    pr = W.burgers2d(96, 0.02)
+    g = hjw.grid_for(pr, FP64)
+    g.set_phi(pr.phi0())
+    g.step_to(0.01, 0.5)
+    g.set_scheme(hjw.WENO_JP)
+    g.step_to(0.02, 0.5)
+    prob_l = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc)
+    prob_j = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc, scheme=O.WENO_JP)
+    ref, info = O.step_to(prob_l, pr.phi0(), 0.01, 0.5)
+    t = info.t
+    while t < 0.02:                          # continue from t = 0.01 with the other scheme
+        ref, info = O.rk3_step(prob_j, ref, t, 0.02, 0.5)
+        t = info.t
+    assert _rel(g.get_phi(), ref) <= 1e-12

@@ -209,3 +209,24 @@ def test_served_workload_sample_holds_fp32_bound():
         err = float(np.abs(recs[rq.rid]["phi"] - ref).max() / np.abs(ref).max())
         assert err < 2e-5, (pr.name, pr.shape, pr.t_final, err)
     srv.close()
+
+
+def test_mixed_schemes_in_one_batch():
+    """WENO-L and WENO-JP requests share the batched launches; each matches hjw_step_to
+    with its own scheme bit for bit."""
+    reqs = _mix(10, seed=31)
+    schemes = [hjw.WENO_JP if k % 2 else hjw.WENO_L for k in range(len(reqs))]
+    srv = hjw.Server(MIXED, pool_bytes=128 << 20, max_active=8)
+    ids = {srv.submit(rq.problem, scheme=sc): (rq, sc) for rq, sc in zip(reqs, schemes)}
+    results = {r.rid: r for r in srv.drain()}
+    srv.close()
+    assert len(results) == len(reqs)
+    for sid, (rq, sc) in ids.items():
+        pr = rq.problem
+        g = hjw.grid_for(pr, MIXED, scheme=sc)
+        g.set_phi(pr.phi0())
+        g.step_to(pr.t_final, pr.cfl)
+        ref = g.get_phi()
+        g.close()
+        assert results[sid].status == hjw.OK
+        assert np.array_equal(results[sid].phi, ref), (pr.name, pr.shape, sc)
