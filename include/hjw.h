@@ -62,10 +62,22 @@ typedef enum { HJW_WENO_L = 0, HJW_WENO_JP = 1 } hjw_scheme;
 /* Built-in Hamiltonians H(u, v), u = phi_x, v = phi_y (v = 0 in 1-D):
  *   LINEAR   p[0]*u + p[1]*v                    (Example 3.1)
  *   BURGERS  (p[0]*u + p[1]*v + p[2])^2 / 2     (Examples 3.3, 3.6)
- *   NEGCOS   -cos(p[0]*u + p[1]*v + p[2])       (Examples 3.2, 3.4)
+ *   NEGCOS   -cos(p[0]*u + p[1]*v + p[2])       (Examples 3.2, 3.4; 3.10 with p[2] = pi/2)
  *   NORM     p[0]*sqrt(u^2 + v^2 + p[1])        (Example 3.12 with p[1] = 1;
- *                                                level-set motion with p[1] = 0) */
-typedef enum { HJW_H_LINEAR = 0, HJW_H_BURGERS = 1, HJW_H_NEGCOS = 2, HJW_H_NORM = 3 } hjw_ham;
+ *                                                level-set motion with p[1] = 0)
+ *   QUARTIC  (s^2 - 1)(s^2 - 4) / 4, s = p[0]*u + p[1]*v + p[2]   (Example 3.8)
+ *   CONTROL  sin(y) u + (sin(x) + sign v) v - sin(y)^2/2 - (1 - cos x), at the node
+ *            (x, y); no parameters                                (Example 3.11)
+ * The dissipation of eq. (LF) is the maximum of |H_u|, |H_v| over the box of the
+ * step's derivative ranges (CONTROL: the bounds 1 and 2 of its coefficients). */
+typedef enum {
+    HJW_H_LINEAR = 0,
+    HJW_H_BURGERS = 1,
+    HJW_H_NEGCOS = 2,
+    HJW_H_NORM = 3,
+    HJW_H_QUARTIC = 4,
+    HJW_H_CONTROL = 5
+} hjw_ham;
 
 /* Options for hjw_set_option. */
 typedef enum {

@@ -33,7 +33,7 @@ _SRC = os.path.join(_HERE, "weno_l_oracle.c")
 _LIB = os.path.join(_HERE, "libhjw_oracle.so")
 
 BC_PERIODIC, BC_EXTRAP = 0, 1
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM = 0, 1, 2, 3
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
 WENO_L, WENO_JP = 0, 1
 
 
@@ -52,7 +52,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
                 ("ham", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("hp", ctypes.c_double * 4),
-                ("scheme", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -85,6 +86,8 @@ def _load():
         lib.orc_arc_length.argtypes = [ctypes.c_double] * 4
         lib.orc_derivatives.restype = ctypes.c_int
         lib.orc_derivatives.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, dp, dp]
+        lib.orc_hamiltonian_at.restype = ctypes.c_double
+        lib.orc_hamiltonian_at.argtypes = [ctypes.POINTER(_Problem)] + [ctypes.c_double] * 4
         lib.orc_hamiltonian.restype = ctypes.c_double
         lib.orc_hamiltonian.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double]
         lib.orc_dissipation.restype = None
@@ -111,13 +114,15 @@ class Problem:
 
     ``shape`` is (nx,) or (ny, nx) (row-major, x fastest); ``h`` is (dx,) or (dx, dy);
     ``bc`` is one code for all axes or a pair (bc_x, bc_y); ``params`` are the
-    Hamiltonian parameters (see ``hamiltonian``); ``scheme`` is WENO_L or WENO_JP."""
+    Hamiltonian parameters (see ``hamiltonian``); ``scheme`` is WENO_L or WENO_JP;
+    ``origin`` is the (x, y) of node 0 (used by the position-dependent H_CONTROL)."""
     shape: tuple
     h: tuple
     ham: int
     params: tuple
     bc: object = BC_PERIODIC
     scheme: int = WENO_L
+    origin: tuple = (0.0, 0.0)
     _c: _Problem = field(init=False, repr=False)
 
     def __post_init__(self):
@@ -133,6 +138,8 @@ class Problem:
         p.bc_x, p.bc_y = int(bcs[0]), int(bcs[1])
         p.ham = int(self.ham)
         p.scheme = int(self.scheme)
+        p.x0 = float(self.origin[0])
+        p.y0 = float(self.origin[1]) if len(self.origin) > 1 else 0.0
         hp = list(self.params) + [0.0] * (4 - len(self.params))
         for k in range(4):
             p.hp[k] = float(hp[k])
@@ -228,8 +235,10 @@ def derivatives(prob: Problem, phi):
     return tuple(outs[:2]) if prob.dim == 1 else tuple(outs)
 
 
-def hamiltonian(prob: Problem, u, v=0.0):
-    return _load().orc_hamiltonian(ctypes.byref(prob._c), float(u), float(v))
+def hamiltonian(prob: Problem, u, v=0.0, x=0.0, y=0.0):
+    """H(u, v) at the node (x, y) (only H_CONTROL depends on the position)."""
+    return _load().orc_hamiltonian_at(ctypes.byref(prob._c), float(x), float(y), float(u),
+                                      float(v))
 
 
 def dissipation(prob: Problem, A, B, C=0.0, D=0.0):

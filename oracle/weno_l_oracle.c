@@ -15,7 +15,8 @@
  *   weno_l_plus           Step 2, "symmetric procedure with respect to x_i"
  *   weno_jp_minus/plus    the comparison scheme of Section 3 (WENO-JP), from its own
  *                         publication (Jiang and Peng, SIAM J. Sci. Comput. 21, 2000)
- *   hamiltonian           the test problems of Section 3 (Examples 3.1-3.4, 3.6, 3.12)
+ *   hamiltonian           the test problems of Section 3 (Examples 3.1-3.4, 3.6, 3.8,
+ *                         3.10-3.12)
  *   dissipation           eq. (LF): alpha = max |H_1| (global box reading, see below)
  *   lax_friedrichs        eq. (LF)
  *   rk3_step              Step 5 (TVD Runge-Kutta, third order)
@@ -46,7 +47,8 @@
 #define ORC_EPS 1.0e-6 /* epsilon of eq. (WLOC1) */
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1 };
-enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3 };
+enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3,
+       ORC_H_QUARTIC = 4, ORC_H_CONTROL = 5 };
 enum { ORC_SCHEME_WENO_L = 0, ORC_SCHEME_WENO_JP = 1 };
 
 typedef struct {
@@ -61,6 +63,8 @@ typedef struct {
     double hp[4];      /* Hamiltonian parameters, see hamiltonian() */
     int32_t scheme;    /* ORC_SCHEME_*: WENO-L (the paper's) or WENO-JP (its comparison) */
     int32_t pad;
+    double x0;         /* coordinates of node (0, 0): the x-dependent Hamiltonian uses them */
+    double y0;
 } orc_problem;
 
 typedef struct {
@@ -313,11 +317,28 @@ int orc_derivatives(const orc_problem *p, const double *phi, double *um, double 
  *   BURGERS  (a u + b v + c)^2 / 2        (Examples 3.3, 3.6)
  *   NEGCOS   -cos(a u + b v + c)          (Examples 3.2, 3.4)
  *   NORM     s sqrt(u^2 + v^2 + k)        (Example 3.12 with k = 1; level-set motion with k = 0)
- * hp = {a, b, c} or {s, k}.  In 1-D v is 0.
+ *   QUARTIC  (s^2 - 1)(s^2 - 4) / 4, s = a u + b v + c   (Example 3.8, nonconvex)
+ *   CONTROL  sin(y) u + (sin(x) + sign v) v - sin(y)^2 / 2 - (1 - cos x)   (Example 3.11)
+ * hp = {a, b, c} or {s, k} (CONTROL has none).  In 1-D v is 0.  (x, y) is the node.
  * ------------------------------------------------------------------------- */
-double orc_hamiltonian(const orc_problem *p, double u, double v)
+static double sign_of(double v)
+{
+    return (v > 0.0) - (v < 0.0);
+}
+
+double orc_hamiltonian_at(const orc_problem *p, double x, double y, double u, double v)
 {
     const double *h = p->hp;
+    switch (p->ham) {
+    case ORC_H_QUARTIC: {
+        const double s = h[0] * u + h[1] * v + h[2];
+        return 0.25 * (s * s - 1.0) * (s * s - 4.0);
+    }
+    case ORC_H_CONTROL:
+        return sin(y) * u + (sin(x) + sign_of(v)) * v - 0.5 * sin(y) * sin(y) - (1.0 - cos(x));
+    default:
+        break;
+    }
     switch (p->ham) {
     case ORC_H_LINEAR:
         return h[0] * u + h[1] * v;
@@ -332,6 +353,28 @@ double orc_hamiltonian(const orc_problem *p, double u, double v)
     default:
         return NAN;
     }
+}
+
+/* H at the origin (the Hamiltonians that do not depend on position). */
+double orc_hamiltonian(const orc_problem *p, double u, double v)
+{
+    return orc_hamiltonian_at(p, 0.0, 0.0, u, v);
+}
+
+/* max of |s^3 - 5 s / 2| (the derivative of the quartic) over [lo, hi]: the ends and the
+ * critical points +-sqrt(5/6) inside */
+static double max_abs_quartic_slope(double lo, double hi)
+{
+    const double sc = sqrt(5.0 / 6.0);
+    double m = 0.0;
+    const double cand[4] = {lo, hi, -sc, sc};
+    for (int k = 0; k < 4; ++k) {
+        const double s = cand[k];
+        if (s < lo || s > hi)
+            continue;
+        m = fmax(m, fabs(s * s * s - 2.5 * s));
+    }
+    return m;
 }
 
 /* max of |sin s| for s in [lo, hi] */
@@ -360,14 +403,17 @@ void orc_dissipation(const orc_problem *p, double A, double B, double C, double 
         *ay = fabs(h[1]);
         return;
     case ORC_H_BURGERS:
-    case ORC_H_NEGCOS: {
+    case ORC_H_NEGCOS:
+    case ORC_H_QUARTIC: {
         /* s = a u + b v + c is linear: its extremes over the box are at corners */
         const double s1 = h[0] * A + h[1] * C + h[2], s2 = h[0] * A + h[1] * D + h[2];
         const double s3 = h[0] * B + h[1] * C + h[2], s4 = h[0] * B + h[1] * D + h[2];
         const double lo = fmin(fmin(s1, s2), fmin(s3, s4));
         const double hi = fmax(fmax(s1, s2), fmax(s3, s4));
-        /* H_1 = a H'(s), H_2 = b H'(s) with H'(s) = s or sin s */
-        const double m = (p->ham == ORC_H_BURGERS) ? fmax(fabs(lo), fabs(hi)) : max_abs_sin(lo, hi);
+        /* H_1 = a H'(s), H_2 = b H'(s) with H'(s) = s, sin s or s^3 - 5s/2 */
+        const double m = (p->ham == ORC_H_BURGERS)  ? fmax(fabs(lo), fabs(hi))
+                         : (p->ham == ORC_H_NEGCOS) ? max_abs_sin(lo, hi)
+                                                    : max_abs_quartic_slope(lo, hi);
         *ax = fabs(h[0]) * m;
         *ay = fabs(h[1]) * m;
         return;
@@ -384,6 +430,11 @@ void orc_dissipation(const orc_problem *p, double A, double B, double C, double 
         *ay = (p->dim == 2) ? fabs(h[0]) * (den_y > 0.0 ? V / sqrt(den_y) : 1.0) : 0.0;
         return;
     }
+    case ORC_H_CONTROL:
+        /* H_1 = sin y, H_2 = sin x + sign v: bounded by 1 and 2 wherever the nodes lie */
+        *ax = 1.0;
+        *ay = (p->dim == 2) ? 2.0 : 0.0;
+        return;
     default:
         *ax = NAN;
         *ay = NAN;
@@ -391,11 +442,17 @@ void orc_dissipation(const orc_problem *p, double A, double B, double C, double 
 }
 
 /* eq. (LF), dimension by dimension */
+double orc_lax_friedrichs_at(const orc_problem *p, double x, double y, double um, double up,
+                             double vm, double vp, double ax, double ay)
+{
+    double H = orc_hamiltonian_at(p, x, y, 0.5 * (up + um), 0.5 * (vp + vm));
+    return H - ax * 0.5 * (up - um) - ay * 0.5 * (vp - vm);
+}
+
 double orc_lax_friedrichs(const orc_problem *p, double um, double up, double vm, double vp,
                           double ax, double ay)
 {
-    double H = orc_hamiltonian(p, 0.5 * (up + um), 0.5 * (vp + vm));
-    return H - ax * 0.5 * (up - um) - ay * 0.5 * (vp - vm);
+    return orc_lax_friedrichs_at(p, 0.0, 0.0, um, up, vm, vp, ax, ay);
 }
 
 /* L(phi) = -H_hat at every node, given alpha. */
@@ -407,7 +464,9 @@ static int operator_L(const orc_problem *p, const double *phi, double ax, double
     const int64_t n = p->nx * p->ny;
     for (int64_t k = 0; k < n; ++k) {
         const double a = (p->dim == 2) ? vm[k] : 0.0, b = (p->dim == 2) ? vp[k] : 0.0;
-        L[k] = -orc_lax_friedrichs(p, um[k], up[k], a, b, ax, ay);
+        const double x = p->x0 + (double)(k % p->nx) * p->dx;
+        const double y = (p->dim == 2) ? p->y0 + (double)(k / p->nx) * p->dy : 0.0;
+        L[k] = -orc_lax_friedrichs_at(p, x, y, um[k], up[k], a, b, ax, ay);
     }
     return 0;
 }

@@ -50,6 +50,7 @@ struct hjw_grid {
     int dim = 0;
     int64_t nx = 0, ny = 1;
     double dx = 0.0, dy = 1.0;
+    double x0 = 0.0, y0 = 0.0;   // coordinates of node (0, 0)
     int bcx = 0, bcy = 0;
     int prec = 0;
     int ham = kHBurgers;
@@ -167,6 +168,10 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     a.remap = (g->dim == 2 && (g->nbx * g->nby) % 8 == 0) ? 1 : 0;
     a.dim = g->dim;
     a.plan_ready = plan_launch(g) ? 1 : 0;
+    a.x0 = g->x0;
+    a.y0 = g->y0;
+    a.dxD = g->dx;
+    a.dyD = g->dy;
     return a;
 }
 
@@ -387,6 +392,9 @@ hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const do
     g->ny = dim == 2 ? n[1] : 1;
     g->dx = (hi[0] - lo[0]) / double(n[0]);
     g->dy = dim == 2 ? (hi[1] - lo[1]) / double(n[1]) : 1.0;
+    // node 0: the low end of a periodic axis, the first cell centre of an extrapolated one
+    g->x0 = lo[0] + (bc[0] == HJW_BC_EXTRAP ? 0.5 * g->dx : 0.0);
+    g->y0 = dim == 2 ? lo[1] + (bc[1] == HJW_BC_EXTRAP ? 0.5 * g->dy : 0.0) : 0.0;
     g->bcx = bc[0];
     g->bcy = dim == 2 ? bc[1] : HJW_BC_PERIODIC;
     g->prec = prec;
@@ -460,7 +468,7 @@ hjw_status hjw_set_scheme(hjw_grid* g, int scheme) {
 
 hjw_status hjw_set_hamiltonian(hjw_grid* g, int kind, const double* params, int nparams) {
     if (!g) return fail(HJW_EINVAL, "grid is NULL");
-    if (kind < HJW_H_LINEAR || kind > HJW_H_NORM)
+    if (kind < HJW_H_LINEAR || kind > HJW_H_CONTROL)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", kind);
     if (nparams < 0 || nparams > 4 || (nparams > 0 && !params))
         return fail(HJW_EINVAL, "bad parameter list");

@@ -24,6 +24,7 @@ namespace {
 int g_tile_rows = 32;  // 2-D tile height being emulated (32 or 16)
 int g_segment = 8;     // nodes per thread in the 2-D sweeps (8, or 4 with 16-row tiles)
 int g_scheme = 0;      // kSchemeL or kSchemeJP
+double g_origin[2] = {0.0, 0.0};   // coordinates of node (0, 0)
 constexpr size_t kGuard = 4096;
 
 template <typename X>
@@ -95,6 +96,10 @@ struct Emu {
         a.epsx = T(weight_eps(g_scheme, pr.dx));
         a.epsy = T(weight_eps(g_scheme, pr.dy));
         a.scheme = g_scheme;
+        a.x0 = g_origin[0];
+        a.y0 = g_origin[1];
+        a.dxD = pr.dx;
+        a.dyD = pr.dy;
         a.ham = pr.ham;
         for (int k = 0; k < 4; ++k) a.hpT[k] = T(pr.hp[k]);
         a.nbx = nbx;
@@ -288,6 +293,12 @@ int hjw_emu_set_tile_rows(int rows) {
     if (rows == 32 && g_segment != 8) return -1;
     g_tile_rows = rows;
     return 0;
+}
+
+// Coordinates of node (0, 0) for the position-dependent Hamiltonian.
+void hjw_emu_set_origin(double x0, double y0) {
+    g_origin[0] = x0;
+    g_origin[1] = y0;
 }
 
 // Scheme of the emulated kernels: 0 WENO-L, 1 WENO-JP.

@@ -203,7 +203,7 @@ hjw_status validate(const hjw_request& r) {
         if (r.bc[d] != HJW_BC_PERIODIC && r.bc[d] != HJW_BC_EXTRAP)
             return fail(HJW_EINVAL, "request axis %d: unknown boundary %d", d, r.bc[d]);
     }
-    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_NORM)
+    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_CONTROL)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", r.ham);
     if (r.scheme != HJW_WENO_L && r.scheme != HJW_WENO_JP)
         return fail(HJW_EINVAL, "unknown scheme %d", r.scheme);
@@ -299,6 +299,10 @@ StageArgs<T, P> request_args(const hjw_server* s, const Req& q) {
     }
     a.ihxD = 1.0 / dx;
     a.ihyD = 1.0 / dy;
+    a.x0 = r.lo[0] + (r.bc[0] == HJW_BC_EXTRAP ? 0.5 * dx : 0.0);
+    a.y0 = r.lo[1] + (r.bc[1] == HJW_BC_EXTRAP ? 0.5 * dy : 0.0);
+    a.dxD = dx;
+    a.dyD = dy;
     a.nbx = int((r.n[0] + kTX - 1) / kTX);
     a.nby = int((r.n[1] + kTY - 1) / kTY);
     a.remap = 0;

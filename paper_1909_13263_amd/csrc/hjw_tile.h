@@ -47,6 +47,8 @@ constexpr int kHLinear = 0;
 constexpr int kHBurgers = 1;
 constexpr int kHNegcos = 2;
 constexpr int kHNorm = 3;
+constexpr int kHQuartic = 4;
+constexpr int kHControl = 5;
 
 // Stage kinds of one Runge-Kutta step.
 constexpr int kStagePre = 0;    // derivatives of phi^n -> Hbar, Dx, Dy, block ranges
@@ -108,6 +110,10 @@ __device__ inline float sqrt_t(float x) { return sqrtf(x); }
 __host__ inline float sqrt_t(float x) { return std::sqrt(x); }
 __device__ inline double sqrt_t(double x) { return sqrt(x); }
 __host__ inline double sqrt_t(double x) { return std::sqrt(x); }
+__device__ inline float sin_t(float x) { return sinf(x); }
+__host__ inline float sin_t(float x) { return std::sin(x); }
+__device__ inline double sin_t(double x) { return sin(x); }
+__host__ inline double sin_t(double x) { return std::sin(x); }
 __device__ inline float cos_t(float x) { return cosf(x); }
 __host__ inline float cos_t(float x) { return std::cos(x); }
 __device__ inline double cos_t(double x) { return cos(x); }
@@ -338,8 +344,13 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
 }
 
 // ---------------------------------------------------------------- Hamiltonians
+// H(u, v) at the node (x, y); only the control Hamiltonian of Example 3.11 depends on
+// the position:
+//   LINEAR a u + b v; BURGERS s^2/2; NEGCOS -cos s; QUARTIC (s^2-1)(s^2-4)/4 with
+//   s = a u + b v + c; NORM k0 sqrt(u^2 + v^2 + k1);
+//   CONTROL sin(y) u + (sin(x) + sign v) v - sin(y)^2/2 - (1 - cos x).
 template <typename T>
-__host__ __device__ inline T hamiltonian(int kind, const T* p, T u, T v) {
+__host__ __device__ inline T hamiltonian(int kind, const T* p, T u, T v, T x, T y) {
     switch (kind) {
     case kHLinear:
         return mul_rn(p[0], u) + mul_rn(p[1], v);
@@ -349,9 +360,32 @@ __host__ __device__ inline T hamiltonian(int kind, const T* p, T u, T v) {
     }
     case kHNegcos:
         return -cos_t((mul_rn(p[0], u) + mul_rn(p[1], v)) + p[2]);
+    case kHQuartic: {
+        const T s = (mul_rn(p[0], u) + mul_rn(p[1], v)) + p[2];
+        const T s2 = s * s;
+        return T(0.25) * ((s2 - T(1)) * (s2 - T(4)));
+    }
+    case kHControl: {
+        const T sy = sin_t(y);
+        const T sgn = T((v > T(0)) - (v < T(0)));
+        return sy * u + (sin_t(x) + sgn) * v - T(0.5) * sy * sy - (T(1) - cos_t(x));
+    }
     default:
         return p[0] * sqrt_t((mul_rn(u, u) + mul_rn(v, v)) + p[1]);
     }
+}
+
+// max of |s^3 - 5s/2| (the slope of the quartic in s) on [lo, hi]: the ends and the
+// critical points +-sqrt(5/6) that lie inside.
+__host__ __device__ inline double max_abs_quartic_slope(double lo, double hi) {
+    const double sc = 0.91287092917527685576;   // sqrt(5/6)
+    double m = 0.0;
+    const double cand[4] = {lo, hi, -sc, sc};
+    for (int k = 0; k < 4; ++k) {
+        const double s = cand[k];
+        if (s >= lo && s <= hi) m = fmax(m, fabs(s * s * s - 2.5 * s));
+    }
+    return m;
 }
 
 // max of |sin s| on [lo, hi]: 1 when a zero of cos lies inside.
@@ -374,7 +408,11 @@ __host__ __device__ inline void dissipation(int kind, const double* p, int dim, 
     if (kind == kHLinear) {
         ax = fabs(p[0]);
         ay = fabs(p[1]);
-    } else if (kind == kHBurgers || kind == kHNegcos) {
+    } else if (kind == kHControl) {
+        // |H_u| = |sin y| <= 1, |H_v| = |sin x + sign v| <= 2 wherever the nodes lie
+        ax = 1.0;
+        ay = dim == 2 ? 2.0 : 0.0;
+    } else if (kind == kHBurgers || kind == kHNegcos || kind == kHQuartic) {
         // s = p0 u + p1 v + p2 takes its extremes on the box at corners
         const double s0 = mul_rn(p[0], A) + mul_rn(p[1], C);
         const double s1 = mul_rn(p[0], A) + mul_rn(p[1], D);
@@ -382,7 +420,9 @@ __host__ __device__ inline void dissipation(int kind, const double* p, int dim, 
         const double s3 = mul_rn(p[0], B) + mul_rn(p[1], D);
         const double lo = fmin(fmin(s0, s1), fmin(s2, s3)) + p[2];
         const double hi = fmax(fmax(s0, s1), fmax(s2, s3)) + p[2];
-        const double m = (kind == kHBurgers) ? fmax(fabs(lo), fabs(hi)) : max_abs_sin(lo, hi);
+        const double m = kind == kHBurgers  ? fmax(fabs(lo), fabs(hi))
+                         : kind == kHNegcos ? max_abs_sin(lo, hi)
+                                            : max_abs_quartic_slope(lo, hi);
         ax = fabs(p[0]) * m;
         ay = fabs(p[1]) * m;
     } else {
@@ -455,6 +495,8 @@ struct StageArgs {
     int dim;
     int plan_ready;   // nonzero: the step plan was published by its own launch
     int scheme;       // kSchemeL or kSchemeJP
+    double x0, y0;    // coordinates of node (0, 0)
+    double dxD, dyD;  // spacing in FP64
 };
 
 // Stage input at a node inside the grid.
@@ -830,7 +872,10 @@ struct Finisher {
         }
         const T ub = T(0.5) * (up + um), vb = T(0.5) * (vp + vm);
         const T Dx = T(0.5) * (up - um), Dy = T(0.5) * (vp - vm);
-        const T H = hamiltonian(a.ham, a.hpT, ub, vb);
+        // node coordinates, for the position-dependent Hamiltonian only
+        const T xn = a.ham == kHControl ? T(a.x0 + double(i) * a.dxD) : T(0);
+        const T yn = a.ham == kHControl ? T(a.y0 + double(j) * a.dyD) : T(0);
+        const T H = hamiltonian(a.ham, a.hpT, ub, vb, xn, yn);
         if (STAGE == kStagePre) {
             reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{H, Dx, Dy};
             lo_u = fmin(lo_u, fmin(um, up));

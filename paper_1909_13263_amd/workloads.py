@@ -13,6 +13,13 @@ Problems (Section 3 of Rathan & Biswas, arXiv:1909.13263, scaled up):
   advect1d    Example 3.1, phi_t + phi_x = 0, phi0 = -cos(pi x) on [-1,1)
   negcos1d    Example 3.2, phi_t - cos(phi_x+1) = 0, phi0 = -cos(pi x) on [-1,1)
 
+Figure-only examples of Section 3 (no printed numbers; see ``figure_examples``):
+  ex35_linear    Example 3.5, phi_t + phi_x = 0, the piecewise phi0(x - 0.5), to t = 2 or 8
+  ex38_quartic   Example 3.8, phi_t + (phi_x^2-1)(phi_x^2-4)/4 = 0, phi0 = -2|x|, to t = 1
+  ex310_sin2d    Example 3.10, phi_t + sin(phi_x+phi_y) = 0, phi0 = pi(|y|-|x|) on [-1,1)^2
+  ex311_control  Example 3.11, the optimal-control equation on [-pi,pi)^2, phi0 = 0, t = 1
+  ex312_eikonal  Example 3.12, phi_t + sqrt(phi_x^2+phi_y^2+1) = 0 on [0,1)^2, t = 0.6
+
 Grid conventions: a periodic axis of n points on [lo, hi) has x_i = lo + i h,
 h = (hi-lo)/n; an extrapolated axis is cell-centred, x_i = lo + (i+1/2) h.
 Arrays are row-major with x fastest: phi[j, i] = phi(x_i, y_j).
@@ -26,7 +33,7 @@ from dataclasses import dataclass
 import numpy as np
 
 BC_PERIODIC, BC_EXTRAP = 0, 1
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM = 0, 1, 2, 3
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
 CIRCLE_SEED = 13263
 SERVE_SEED = 1909
 
@@ -96,6 +103,60 @@ def levelset2d(n=4096, t_final=0.2, seed=CIRCLE_SEED, ny=None):
                    (1.0, 0.0), t_final, seed=seed)
 
 
+def ex35_linear(n=100, t_final=2.0):
+    return Problem("ex35_linear", (n,), (-1.0,), (1.0,), BC_PERIODIC, H_LINEAR, (1.0, 0.0),
+                   t_final)
+
+
+def ex38_quartic(n=100, t_final=1.0):
+    return Problem("ex38_quartic", (n,), (-1.0,), (1.0,), BC_PERIODIC, H_QUARTIC,
+                   (1.0, 0.0, 0.0), t_final)
+
+
+def ex310_sin2d(n=80, t_final=1.0):
+    # sin(s) = -cos(s + pi/2)
+    return Problem("ex310_sin2d", (n, n), (-1.0, -1.0), (1.0, 1.0), BC_PERIODIC, H_NEGCOS,
+                   (1.0, 1.0, 0.5 * math.pi), t_final)
+
+
+def ex311_control(n=60, t_final=1.0):
+    return Problem("ex311_control", (n, n), (-math.pi, -math.pi), (math.pi, math.pi),
+                   BC_PERIODIC, H_CONTROL, (), t_final)
+
+
+def ex312_eikonal(n=80, t_final=0.6):
+    return Problem("ex312_eikonal", (n, n), (0.0, 0.0), (1.0, 1.0), BC_PERIODIC, H_NORM,
+                   (1.0, 1.0), t_final)
+
+
+def figure_examples():
+    """The figure-only examples of Section 3 at the paper's grid sizes and times (with
+    the 1-D Burgers and -cos runs past the kink time, Examples 3.6 and 3.7, and the 2-D
+    Burgers run of Example 3.9)."""
+    return [ex35_linear(100, 2.0), ex35_linear(100, 8.0), burgers1d(40, 3.5 / math.pi**2),
+            negcos1d(80, 1.5 / math.pi**2), ex38_quartic(100, 1.0),
+            burgers2d(40, 1.5 / math.pi**2), ex310_sin2d(80, 1.0), ex311_control(60, 1.0),
+            ex312_eikonal(80, 0.6)]
+
+
+def ex35_phi0(x):
+    """The piecewise initial profile of Example 3.5 (before its shift by 0.5), on [-1,1).
+    The third piece is 15/2 - 3 cos(2 pi x): with the printed 5/2 the profile would jump by
+    5 at x = 0 and at x = 1/3, while 15/2 makes it continuous at both (and the linear part
+    makes it periodic)."""
+    x = np.asarray(x, dtype=np.float64)
+    lin = -(math.sqrt(3) / 2 + 4.5 + 2 * math.pi / 3) * (x + 1)
+    out = np.where(x < -1 / 3, 2 * np.cos(1.5 * math.pi * x**2) - math.sqrt(3),
+          np.where(x < 0, 1.5 + 3 * np.cos(2 * math.pi * x),
+          np.where(x < 1 / 3, 7.5 - 3 * np.cos(2 * math.pi * x),
+                   (28 + 4 * math.pi + np.cos(3 * math.pi * x)) / 3 + 6 * math.pi * x * (x - 1))))
+    return lin + out
+
+
+def wrap_periodic(x, lo=-1.0, hi=1.0):
+    return lo + np.mod(np.asarray(x) - lo, hi - lo)
+
+
 def circles(seed=CIRCLE_SEED, count=64):
     """Centres uniform in [0.1,0.9]^2 (drawn first), then radii uniform in [0.02,0.08]."""
     rng = np.random.default_rng(seed)
@@ -108,6 +169,18 @@ def initial_data(p: Problem) -> np.ndarray:
     if p.name in ("burgers1d", "advect1d", "negcos1d"):
         x = p.coords(0)
         return -np.cos(math.pi * x)
+    if p.name == "ex35_linear":
+        return ex35_phi0(wrap_periodic(p.coords(0) - 0.5))
+    if p.name == "ex38_quartic":
+        return -2.0 * np.abs(p.coords(0))
+    if p.name == "ex310_sin2d":
+        x, y = p.coords(0), p.coords(1)
+        return math.pi * (np.abs(y)[:, None] - np.abs(x)[None, :])
+    if p.name == "ex311_control":
+        return np.zeros(p.shape)
+    if p.name == "ex312_eikonal":
+        x, y = p.coords(0), p.coords(1)
+        return 0.25 * (np.cos(2 * math.pi * x)[None, :] - 1) * (np.cos(2 * math.pi * y)[:, None] - 1) - 1
     if p.name in ("burgers2d", "negcos2d"):
         x = p.coords(0)
         y = p.coords(1)

@@ -27,6 +27,8 @@ def lib():
         L.hjw_emu_set_segment.argtypes = [ctypes.c_int]
         L.hjw_emu_set_scheme.restype = ctypes.c_int
         L.hjw_emu_set_scheme.argtypes = [ctypes.c_int]
+        L.hjw_emu_set_origin.restype = None
+        L.hjw_emu_set_origin.argtypes = [ctypes.c_double, ctypes.c_double]
         L.hjw_emu_step.restype = ctypes.c_int
         L.hjw_emu_step.argtypes = [ctypes.c_int, i64, i64, d, d, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, vp, vp, d, d, d, vp]
@@ -41,6 +43,11 @@ def set_tile_rows(rows):
 def set_scheme(scheme):
     """0 WENO-L, 1 WENO-JP for the emulated kernels."""
     assert lib().hjw_emu_set_scheme(int(scheme)) == 0
+
+
+def set_origin(x0, y0=0.0):
+    """Coordinates of node (0, 0) for the position-dependent Hamiltonians."""
+    lib().hjw_emu_set_origin(float(x0), float(y0))
 
 
 def set_tile(rows, segment):

@@ -119,3 +119,32 @@ def test_emulated_jp_rk3_step_matches_oracle(case, prec, weno_jp):
     assert rc == 0
     assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
     assert np.abs(got - ref).max() <= {0: 1e-14, 1: 1e-7}[prec] * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------- figure examples
+def _origin(pr):
+    return tuple(pr.coords(a)[0] for a in range(pr.dim)) + (0.0,) * (2 - pr.dim)
+
+
+@pytest.mark.parametrize("name", ["ex35", "ex38", "ex310", "ex311", "ex312"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_emulated_figure_examples_match_oracle(name, prec, tile_rows):
+    """The Hamiltonians of Examples 3.5 and 3.8-3.12 (the quartic, the position-dependent
+    control problem with node coordinates, the sqrt form) in the tile code, one step
+    from a state part way along the solve."""
+    pr = {"ex35": lambda: W.ex35_linear(160, 0.5), "ex38": lambda: W.ex38_quartic(100, 0.2),
+          "ex310": lambda: W.ex310_sin2d(70, 0.2), "ex311": lambda: W.ex311_control(66, 0.2),
+          "ex312": lambda: W.ex312_eikonal(72, 0.2)}[name]()
+    x0, y0 = _origin(pr)
+    EM.set_origin(x0, y0)
+    try:
+        prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc, origin=(x0, y0))
+        phi, _ = O.rk3_step(prob, pr.phi0(), 0.0, pr.t_final, 0.5)
+        ref, info = O.rk3_step(prob, phi, 0.0, pr.t_final, 0.5)
+        rc, got, ei = EM.rk3_step(phi, pr.spacing, pr.ham, pr.params, 0.0, pr.t_final, 0.5,
+                                  pr.bc, prec)
+    finally:
+        EM.set_origin(0.0, 0.0)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    assert np.abs(got - ref).max() <= {0: 1e-14, 1: 1e-7}[prec] * np.abs(ref).max()
