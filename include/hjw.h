@@ -42,7 +42,17 @@ typedef enum {
     HJW_EBUSY = -6       /* resource in use                                      */
 } hjw_status;
 
-typedef enum { HJW_BC_PERIODIC = 0, HJW_BC_EXTRAP = 1 } hjw_bc;
+/* Boundary per axis:
+ *   HJW_BC_PERIODIC   nodes x_i = lo + i h, h = (hi - lo)/n, wrapped;
+ *   HJW_BC_EXTRAP     cell-centred nodes x_i = lo + (i + 1/2) h, three ghosts on each
+ *                     side extrapolated linearly through the two end nodes;
+ *   HJW_BC_DIRICHLET  nodes x_i = lo + i h; the three outermost node layers hold the
+ *                     boundary data (their values in the phi given to hjw_set_phi, or
+ *                     to hjw_server_submit) and are never updated; their derivatives
+ *                     are left out of the dissipation ranges.  Needs n >= 7 (n >= 8
+ *                     holds for every grid).  Example 3.10 of Section 3 names a
+ *                     Dirichlet boundary without its data; this is the reading. */
+typedef enum { HJW_BC_PERIODIC = 0, HJW_BC_EXTRAP = 1, HJW_BC_DIRICHLET = 2 } hjw_bc;
 
 /* Arithmetic of the stencil (candidates, indicators, weights, flux):
  *   HJW_FP64        everything in FP64;

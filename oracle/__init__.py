@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "weno_l_oracle.c")
 _LIB = os.path.join(_HERE, "libhjw_oracle.so")
 
-BC_PERIODIC, BC_EXTRAP = 0, 1
+BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
 H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
 WENO_L, WENO_JP = 0, 1
 

@@ -37,7 +37,12 @@
  *     brute-force sampling of the box in the tests.
  *   - dt = cfl / (alpha_x/dx + alpha_y/dy), clamped to t_final - t (the paper
  *     gives only the CFL number).  PARITY UNPINNED by the paper (a reading).
- *   - Boundaries: periodic wrap, or linear extrapolation into three ghosts.
+ *   - Boundaries: periodic wrap, or linear extrapolation into three ghosts, or
+ *     Dirichlet data: the three outermost node layers of such an axis carry the
+ *     boundary values (those of phi at t = 0), are never updated, and are left out
+ *     of the derivative ranges; every other node's stencil lies inside the grid.
+ *     Example 3.10 names a Dirichlet boundary without giving the data: this is the
+ *     reading.  PARITY UNPINNED by the paper (a reading).
  */
 #include <math.h>
 #include <stdint.h>
@@ -46,7 +51,7 @@
 
 #define ORC_EPS 1.0e-6 /* epsilon of eq. (WLOC1) */
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1, ORC_BC_DIRICHLET = 2 };
 enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3,
        ORC_H_QUARTIC = 4, ORC_H_CONTROL = 5 };
 enum { ORC_SCHEME_WENO_L = 0, ORC_SCHEME_WENO_JP = 1 };
@@ -246,7 +251,9 @@ double orc_weno_jp_plus(const double g[6], double dx, double *is_out, double *om
 
 /* ---------------------------------------------------------------------------
  * Ghost values: three per side.  periodic wraps; extrapolation continues the
- * line through the two end points.
+ * line through the two end points.  A Dirichlet axis uses the extrapolated
+ * values too, but only its held nodes (below) read them, and those nodes' results
+ * are discarded.
  * ------------------------------------------------------------------------- */
 static void fill_line(const double *src, int64_t stride, int64_t n, int bc, double *ext /* n+6 */)
 {
@@ -455,7 +462,19 @@ double orc_lax_friedrichs(const orc_problem *p, double um, double up, double vm,
     return orc_lax_friedrichs_at(p, 0.0, 0.0, um, up, vm, vp, ax, ay);
 }
 
-/* L(phi) = -H_hat at every node, given alpha. */
+/* A node in one of the three outermost layers of a Dirichlet axis: it keeps its
+ * value, and its derivatives enter neither the ranges nor the update. */
+static int held(const orc_problem *p, int64_t k)
+{
+    const int64_t i = k % p->nx, j = k / p->nx;
+    if (p->bc_x == ORC_BC_DIRICHLET && (i < 3 || i >= p->nx - 3))
+        return 1;
+    if (p->dim == 2 && p->bc_y == ORC_BC_DIRICHLET && (j < 3 || j >= p->ny - 3))
+        return 1;
+    return 0;
+}
+
+/* L(phi) = -H_hat at every node, given alpha (0 at held nodes). */
 static int operator_L(const orc_problem *p, const double *phi, double ax, double ay, double *L,
                       double *um, double *up, double *vm, double *vp)
 {
@@ -466,7 +485,7 @@ static int operator_L(const orc_problem *p, const double *phi, double ax, double
         const double a = (p->dim == 2) ? vm[k] : 0.0, b = (p->dim == 2) ? vp[k] : 0.0;
         const double x = p->x0 + (double)(k % p->nx) * p->dx;
         const double y = (p->dim == 2) ? p->y0 + (double)(k / p->nx) * p->dy : 0.0;
-        L[k] = -orc_lax_friedrichs_at(p, x, y, um[k], up[k], a, b, ax, ay);
+        L[k] = held(p, k) ? 0.0 : -orc_lax_friedrichs_at(p, x, y, um[k], up[k], a, b, ax, ay);
     }
     return 0;
 }
@@ -482,6 +501,12 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
     double *um = malloc(bytes), *up = malloc(bytes), *vm = malloc(bytes), *vp = malloc(bytes);
     double *L = malloc(bytes), *p0 = malloc(bytes), *p1 = malloc(bytes), *p2 = malloc(bytes);
     int rc = 0;
+    /* a Dirichlet axis needs at least one node beyond its six held layers */
+    if ((p->bc_x == ORC_BC_DIRICHLET && p->nx < 7) ||
+        (p->dim == 2 && p->bc_y == ORC_BC_DIRICHLET && p->ny < 7)) {
+        rc = -1;
+        goto out;
+    }
     if (!um || !up || !vm || !vp || !L || !p0 || !p1 || !p2) {
         rc = -1;
         goto out;
@@ -499,6 +524,8 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
         D = -INFINITY;
     }
     for (int64_t k = 0; k < n; ++k) {
+        if (held(p, k))
+            continue;
         A = fmin(A, fmin(um[k], up[k]));
         B = fmax(B, fmax(um[k], up[k]));
         if (p->dim == 2) {
@@ -524,15 +551,15 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
     /* phi_1 = phi_0 + dt L(phi_0) */
     if (operator_L(p, p0, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
     for (int64_t k = 0; k < n; ++k)
-        p1[k] = p0[k] + dt * L[k];
+        p1[k] = held(p, k) ? p0[k] : p0[k] + dt * L[k];
     /* phi_2 = 3/4 phi_0 + 1/4 (phi_1 + dt L(phi_1)) */
     if (operator_L(p, p1, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
     for (int64_t k = 0; k < n; ++k)
-        p2[k] = 0.75 * p0[k] + 0.25 * (p1[k] + dt * L[k]);
+        p2[k] = held(p, k) ? p0[k] : 0.75 * p0[k] + 0.25 * (p1[k] + dt * L[k]);
     /* phi^{n+1} = 1/3 phi_0 + 2/3 (phi_2 + dt L(phi_2)) */
     if (operator_L(p, p2, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
     for (int64_t k = 0; k < n; ++k) {
-        phi[k] = (1.0 / 3.0) * p0[k] + (2.0 / 3.0) * (p2[k] + dt * L[k]);
+        phi[k] = held(p, k) ? p0[k] : (1.0 / 3.0) * p0[k] + (2.0 / 3.0) * (p2[k] + dt * L[k]);
         if (!isfinite(phi[k]))
             rc = -2;
     }

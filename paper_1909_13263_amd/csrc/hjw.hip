@@ -379,7 +379,8 @@ hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const do
         if (n[d] < 8) return fail(HJW_EINVAL, "n[%d] = %lld < 8", d, (long long)n[d]);
         if (!(hi[d] > lo[d]) || !std::isfinite(lo[d]) || !std::isfinite(hi[d]))
             return fail(HJW_EINVAL, "axis %d: need finite lo < hi", d);
-        if (bc[d] != HJW_BC_PERIODIC && bc[d] != HJW_BC_EXTRAP)
+        if (bc[d] != HJW_BC_PERIODIC && bc[d] != HJW_BC_EXTRAP &&
+            bc[d] != HJW_BC_DIRICHLET)
             return fail(HJW_EINVAL, "axis %d: unknown boundary %d", d, bc[d]);
     }
     if (n[0] > (int64_t(1) << 30) || (dim == 2 && n[1] > (int64_t(1) << 30)) ||

@@ -200,7 +200,8 @@ hjw_status validate(const hjw_request& r) {
                         (long long)r.n[d]);
         if (!(r.hi[d] > r.lo[d]) || !std::isfinite(r.lo[d]) || !std::isfinite(r.hi[d]))
             return fail(HJW_EINVAL, "request axis %d: need finite lo < hi", d);
-        if (r.bc[d] != HJW_BC_PERIODIC && r.bc[d] != HJW_BC_EXTRAP)
+        if (r.bc[d] != HJW_BC_PERIODIC && r.bc[d] != HJW_BC_EXTRAP &&
+            r.bc[d] != HJW_BC_DIRICHLET)
             return fail(HJW_EINVAL, "request axis %d: unknown boundary %d", d, r.bc[d]);
     }
     if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_CONTROL)

@@ -43,6 +43,10 @@ namespace hjw {
 
 constexpr int kBcPeriodic = 0;
 constexpr int kBcExtrap = 1;
+// Dirichlet: the three outermost node layers of the axis hold boundary data; they keep
+// their values, and their derivatives enter neither the ranges nor the update.  Loads
+// treat the axis as extrapolated: only those layers read the ghosts.
+constexpr int kBcDirichlet = 2;
 constexpr int kHLinear = 0;
 constexpr int kHBurgers = 1;
 constexpr int kHNegcos = 2;
@@ -855,6 +859,11 @@ struct Finisher {
         : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), lo_u(T(INFINITY)),
           hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {}
 
+    __host__ __device__ bool held(int64_t i, int64_t j) const {
+        return (a.bcx == kBcDirichlet && (i < 3 || i >= a.nx - 3)) ||
+               (dim == 2 && a.bcy == kBcDirichlet && (j < 3 || j >= a.ny - 3));
+    }
+
     // ps: the stage input at the node (phi_1 in the second stage, phi_2 in the third);
     // pn: phi^n at the node (second and third stages).
     __host__ __device__ void operator()(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
@@ -868,6 +877,12 @@ struct Finisher {
                 a.dout2[idx] = double(vm);
                 a.dout3[idx] = double(vp);
             }
+            return;
+        }
+        const bool hold = held(i, j);
+        if (STAGE == kStagePre && hold) {
+            // phi_1 = phi^n - dt (0 - 0) is phi^n exactly
+            reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{T(0), T(0), T(0)};
             return;
         }
         const T ub = T(0.5) * (up + um), vb = T(0.5) * (vp + vm);
@@ -894,7 +909,7 @@ struct Finisher {
         } else {
             res = (1.0 / 3.0) * pn + (2.0 / 3.0) * (double(ps) - dt * double(R));
         }
-        const P outv = P(res);
+        const P outv = hold ? pn_ : P(res);
         a.out[idx] = outv;
         if (!finite_t(outv)) bad = true;
     }

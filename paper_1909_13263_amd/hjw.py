@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhjw.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5, -6
-BC_PERIODIC, BC_EXTRAP = 0, 1
+BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
 FP64, FP32_MIXED, FP32 = 0, 1, 2
 H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
 WENO_L, WENO_JP = 0, 1

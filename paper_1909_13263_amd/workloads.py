@@ -32,7 +32,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-BC_PERIODIC, BC_EXTRAP = 0, 1
+BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
 H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
 CIRCLE_SEED = 13263
 SERVE_SEED = 1909
@@ -115,7 +115,7 @@ def ex38_quartic(n=100, t_final=1.0):
 
 def ex310_sin2d(n=80, t_final=1.0):
     # sin(s) = -cos(s + pi/2)
-    return Problem("ex310_sin2d", (n, n), (-1.0, -1.0), (1.0, 1.0), BC_PERIODIC, H_NEGCOS,
+    return Problem("ex310_sin2d", (n, n), (-1.0, -1.0), (1.0, 1.0), BC_DIRICHLET, H_NEGCOS,
                    (1.0, 1.0, 0.5 * math.pi), t_final)
 
 

@@ -53,6 +53,13 @@ def test_create_rejects_bad_arguments(args, msg):
     assert not h.value
 
 
+@pytest.mark.parametrize("bc", [[2, 2], [2, 0], [1, 2]])
+def test_create_accepts_dirichlet(bc):
+    rc, h = _create(2, [16, 9], [-1, -1], [1, 1], bc, hjw.FP64)
+    assert rc == 0 and h.value
+    hjw.lib().hjw_grid_destroy(h)
+
+
 @pytest.mark.parametrize("prec,per_cell", [(hjw.FP64, 40), (hjw.FP32_MIXED, 28), (hjw.FP32, 20)])
 def test_workspace_is_the_hbm_footprint(prec, per_cell):
     """phi + stage buffer + three flux arrays per cell, plus block partials and state."""

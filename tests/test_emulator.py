@@ -148,3 +148,29 @@ def test_emulated_figure_examples_match_oracle(name, prec, tile_rows):
     assert rc == 0
     assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
     assert np.abs(got - ref).max() <= {0: 1e-14, 1: 1e-7}[prec] * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("shape", [(37,), (8, 8), (33, 65), (100, 200), (135, 260)])
+@pytest.mark.parametrize("bc", [(2, 2), (2, 0), (0, 2), (1, 2)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_dirichlet_step_matches_oracle(shape, bc, prec, tile_rows):
+    """Held boundary layers on ragged grids, alone and beside the other boundaries."""
+    if len(shape) == 1 and bc[1] != 2:
+        return
+    bcs = bc if len(shape) == 2 else (bc[0], bc[0])
+    h = tuple(0.05 + 0.01 * a for a in range(len(shape)))
+    phi = W.random_smooth_periodic(shape, seed=sum(shape) + 3)
+    prob = O.Problem(shape, h, O.H_BURGERS, (1.0, 1.0, 1.0), bcs)
+    ref, info = O.rk3_step(prob, phi, 0.0, 1.0, 0.5)
+    rc, got, ei = EM.rk3_step(phi, h, O.H_BURGERS, (1.0, 1.0, 1.0), 0.0, 1.0, 0.5, bcs, prec)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    assert list(ei[4:8]) == pytest.approx(list(info.range), rel=1e-12 if prec == 0 else 1e-5)
+    assert np.abs(got - ref).max() <= {0: 1e-14, 1: 1e-7, 2: 1e-6}[prec] * np.abs(ref).max()
+    held = np.zeros(phi.shape, bool)
+    if bcs[0] == 2:
+        held[..., :3] = held[..., -3:] = True
+    if len(shape) == 2 and bcs[1] == 2:
+        held[:3, :] = held[-3:, :] = True
+    p_cast = phi if prec < 2 else phi.astype(np.float32).astype(np.float64)
+    assert np.array_equal(got[held], p_cast[held])

@@ -85,3 +85,85 @@ def test_two_d_examples_through_the_server():
         assert results[sid].status == hjw.OK
         assert results[sid].info.steps == info.steps
         assert np.array_equal(results[sid].phi, ref), pr.name
+
+
+# --------------------------------------------------------------------------- Dirichlet
+DIRICHLET_CASES = [((135, 200), (2, 2)), ((135, 200), (2, 0)), ((70, 260), (0, 2)),
+                   ((100, 130), (1, 2)), ((1000,), (2, 2))]
+
+
+def _dirichlet(shape, bc, t_final=0.01):
+    """Burgers' H on [-1, 1)^d with random smooth data held on the Dirichlet layers.  Held
+    data at an outflow boundary builds a steepening layer (dt falls twenty-fold by
+    t = 0.05, and rounding differences grow there in any two implementations), so the
+    horizon is kept to the first 100-200 steps."""
+    lo, hi = (-1.0,) * len(shape), (1.0,) * len(shape)
+    return W.Problem("dirichlet_burgers", shape, lo, hi, bc if len(shape) == 2 else bc[0],
+                     W.H_BURGERS, (1.0, 1.0, 1.0), t_final)
+
+
+@pytest.mark.parametrize("shape,bc", DIRICHLET_CASES, ids=[f"{s}-{b}" for s, b in DIRICHLET_CASES])
+def test_dirichlet_whole_solves(shape, bc):
+    """Held layers on ragged multi-tile grids, alone and beside the other boundaries: FP64
+    within 1e-12 of the oracle, the FP32 paths within the usual bounds, and the held
+    layers bitwise unchanged."""
+    pr = _dirichlet(shape, bc)
+    phi0 = W.random_smooth_periodic(shape, seed=sum(shape))
+    bcs = bc if len(shape) == 2 else (bc[0], bc[0])
+    prob = O.Problem(shape, pr.spacing, pr.ham, pr.params, bcs)
+    ref, info = O.step_to(prob, phi0, pr.t_final, pr.cfl)
+    held = np.zeros(shape, bool)
+    if bcs[0] == W.BC_DIRICHLET:
+        held[..., :3] = held[..., -3:] = True
+    if len(shape) == 2 and bcs[1] == W.BC_DIRICHLET:
+        held[:3] = held[-3:] = True
+    for prec, tol in [(FP64, 1e-12), (MIXED, 2e-6), (FP32, 2e-5)]:
+        g = hjw.Grid(shape, pr.lo, pr.hi, bcs if len(shape) == 2 else bcs[0], prec)
+        g.set_hamiltonian(pr.ham, pr.params)
+        g.set_phi(phi0)
+        gi = g.step_to(pr.t_final, pr.cfl)
+        phi = g.get_phi()
+        g.close()
+        assert abs(gi.steps - info.steps) <= (0 if prec == FP64 else 1)
+        err = float(np.abs(phi - ref).max() / np.abs(ref).max())
+        print(f"dirichlet {shape} bc={bc} prec={prec} rel={err:.3e}", flush=True)
+        assert err <= tol
+        p0 = phi0 if prec != FP32 else phi0.astype(np.float32).astype(np.float64)
+        assert np.array_equal(phi[held], p0[held])
+
+
+def test_dirichlet_full_size_steps():
+    """A 1024^2 Dirichlet grid in the benchmark's launch configuration: three steps."""
+    shape = (1024, 1024)
+    pr = _dirichlet(shape, (2, 2))
+    phi0 = W.random_smooth_periodic(shape, seed=5)
+    ref, _ = O.step_to(O.Problem(shape, pr.spacing, pr.ham, pr.params, (2, 2)), phi0, 1.0,
+                       pr.cfl, max_steps=3)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 1e-6)]:
+        g = hjw.Grid(shape, pr.lo, pr.hi, (2, 2), prec)
+        g.set_hamiltonian(pr.ham, pr.params)
+        g.set_phi(phi0)
+        g.step_to(1.0, pr.cfl, max_steps=3)
+        err = float(np.abs(g.get_phi() - ref).max() / np.abs(ref).max())
+        g.close()
+        assert err <= tol, (prec, err)
+
+
+def test_dirichlet_requests_through_the_server():
+    probs = [_dirichlet((135, 200), (2, 2)), _dirichlet((64, 90), (2, 0)),
+             W.ex310_sin2d(80, 0.5)]
+    srv = hjw.Server(MIXED, pool_bytes=64 << 20, max_active=8)
+    ids = {srv.submit(pr, pr.phi0() if pr.name.startswith("ex") else
+                      W.random_smooth_periodic(pr.shape, seed=1)): pr for pr in probs}
+    results = {r.rid: r for r in srv.drain()}
+    srv.close()
+    for sid, pr in ids.items():
+        phi0 = pr.phi0() if pr.name.startswith("ex") else W.random_smooth_periodic(pr.shape, seed=1)
+        g = hjw.Grid(pr.shape, pr.lo, pr.hi, pr.bc, MIXED)
+        g.set_hamiltonian(pr.ham, pr.params)
+        g.set_phi(phi0)
+        g.step_to(pr.t_final, pr.cfl)
+        ref = g.get_phi()
+        g.close()
+        assert results[sid].status == hjw.OK
+        assert np.array_equal(results[sid].phi, ref), pr.name

@@ -122,3 +122,76 @@ def test_example312_descends_at_unit_speed_or_faster():
     pr = W.ex312_eikonal(80, 0.6)
     phi, _ = O.step_to(_problem(pr), pr.phi0(), 0.6, 0.5)
     assert (phi - (pr.phi0() - 0.6)).max() <= 1e-5
+
+
+# --------------------------------------------------------------------------- Dirichlet
+def _dirichlet_problem(shape, bc, ham=O.H_BURGERS, params=(1.0, 1.0, 1.0)):
+    h = tuple(2.0 / n for n in shape[::-1])
+    return O.Problem(shape, h, ham, params, bc)
+
+
+@pytest.mark.parametrize("bc", [(O.BC_DIRICHLET, O.BC_DIRICHLET), (O.BC_DIRICHLET, O.BC_PERIODIC),
+                                (O.BC_PERIODIC, O.BC_DIRICHLET)])
+def test_dirichlet_layers_keep_their_values(bc):
+    shape = (37, 50)
+    prob = _dirichlet_problem(shape, bc)
+    phi0 = W.random_smooth_periodic(shape, seed=4)
+    phi, info = O.step_to(prob, phi0, 0.05, 0.5)
+    assert info.steps > 3
+    held = np.zeros(shape, bool)
+    if bc[0] == O.BC_DIRICHLET:
+        held[:, :3] = held[:, -3:] = True
+    if bc[1] == O.BC_DIRICHLET:
+        held[:3, :] = held[-3:, :] = True
+    assert np.array_equal(phi[held], phi0[held])
+    assert np.abs(phi[~held] - phi0[~held]).min() > 0 or np.abs(phi - phi0).max() > 1e-3
+
+
+def test_dirichlet_interior_follows_the_periodic_solve_until_the_boundary_is_felt():
+    """With H linear the dissipation does not depend on the ranges, so a Dirichlet solve and
+    a periodic solve of the same data differ only inside the numerical domain of dependence
+    of the held layers: 3 nodes per stage, starting from the stage after the first."""
+    shape = (120,)
+    phi0 = W.random_smooth_periodic(shape, seed=12)
+    per = O.Problem(shape, (2 / 120,), O.H_LINEAR, (1.0, 0.0), O.BC_PERIODIC)
+    dir_ = O.Problem(shape, (2 / 120,), O.H_LINEAR, (1.0, 0.0), O.BC_DIRICHLET)
+    for steps in (1, 2, 4):
+        a, ia = O.step_to(per, phi0, 1.0, 0.5, max_steps=steps)
+        b, ib = O.step_to(dir_, phi0, 1.0, 0.5, max_steps=steps)
+        assert ia.t == ib.t
+        reach = 3 + 3 * (3 * steps - 1)
+        inner = slice(reach, 120 - reach)
+        assert np.array_equal(a[inner], b[inner]), steps
+        assert not np.array_equal(a[3:reach + 3], b[3:reach + 3])
+
+
+def test_dirichlet_layers_stay_out_of_the_ranges():
+    """Steep data confined to the held layers does not raise the dissipation: the ranges of
+    a step are those of the derivatives at the free nodes."""
+    shape = (40, 40)
+    prob = _dirichlet_problem(shape, O.BC_DIRICHLET)
+    phi0 = W.random_smooth_periodic(shape, seed=8)
+    phi0[:, :2] += 50.0 * np.arange(2)[None, :]
+    um, up, vm, vp = O.derivatives(prob, phi0)
+    free = np.zeros(shape, bool)
+    free[3:-3, 3:-3] = True
+    _, info = O.rk3_step(prob, phi0, 0.0, 1.0, 0.5)
+    assert info.range == pytest.approx([min(um[free].min(), up[free].min()),
+                                        max(um[free].max(), up[free].max()),
+                                        min(vm[free].min(), vp[free].min()),
+                                        max(vm[free].max(), vp[free].max())], abs=0)
+    assert max(abs(um).max(), abs(up).max()) > 10 * max(abs(info.range[0]), abs(info.range[1]))
+
+
+def test_example310_dirichlet_corners_and_symmetry():
+    """phi0 = pi(|y| - |x|) is piecewise linear with H = sin(phi_x + phi_y) = 0 on each
+    piece: the boundary layers hold +-pi at the corners.  psi(x, y) = -phi(y, x) solves the
+    same equation (psi_x + psi_y = -(phi_x + phi_y) at the swapped point, and sin is odd)
+    from the same data, so phi = -phi^T on the symmetric grid, to rounding."""
+    pr = W.ex310_sin2d(80, 1.0)
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc, origin=(-1.0, -1.0))
+    phi, _ = O.step_to(prob, pr.phi0(), 1.0, 0.5)
+    assert phi.max() == pytest.approx(math.pi, abs=1e-15) and phi.min() == pytest.approx(-math.pi, abs=1e-15)
+    assert np.isfinite(phi).all()
+    assert np.abs(phi + phi.T).max() <= 1e-13
+    assert np.abs(phi + phi.T).max() <= 1e-13
