@@ -78,6 +78,13 @@ typedef enum { HJW_WENO_L = 0, HJW_WENO_JP = 1 } hjw_scheme;
  *   QUARTIC  (s^2 - 1)(s^2 - 4) / 4, s = p[0]*u + p[1]*v + p[2]   (Example 3.8)
  *   CONTROL  sin(y) u + (sin(x) + sign v) v - sin(y)^2/2 - (1 - cos x), at the node
  *            (x, y); no parameters                                (Example 3.11)
+ *   CURVATURE p[0]*sqrt(u^2 + v^2 + p[1]) plus the curvature term of Example 3.13 with
+ *            weight eps = p[2] >= 0: the operator gains eps N / (1 + phi_x^2 + phi_y^2),
+ *            N = (1 + phi_y^2) phi_xx - 2 phi_x phi_y phi_xy + (1 + phi_x^2) phi_yy, from
+ *            second-order central differences over the node's 3 x 3 neighbourhood, and
+ *            the time-step rate gains 2 eps (1/dx^2 + 1/dy^2).  Example 3.13 is
+ *            p = {-1, 1, eps}.  2-D grids with periodic or Dirichlet axes only (EINVAL
+ *            otherwise).
  * The dissipation of eq. (LF) is the maximum of |H_u|, |H_v| over the box of the
  * step's derivative ranges (CONTROL: the bounds 1 and 2 of its coefficients). */
 typedef enum {
@@ -86,7 +93,8 @@ typedef enum {
     HJW_H_NEGCOS = 2,
     HJW_H_NORM = 3,
     HJW_H_QUARTIC = 4,
-    HJW_H_CONTROL = 5
+    HJW_H_CONTROL = 5,
+    HJW_H_CURVATURE = 6
 } hjw_ham;
 
 /* Options for hjw_set_option. */

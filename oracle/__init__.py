@@ -33,7 +33,7 @@ _SRC = os.path.join(_HERE, "weno_l_oracle.c")
 _LIB = os.path.join(_HERE, "libhjw_oracle.so")
 
 BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE = 0, 1, 2, 3, 4, 5, 6
 WENO_L, WENO_JP = 0, 1
 
 
@@ -94,6 +94,9 @@ def _load():
         lib.orc_dissipation.argtypes = [ctypes.POINTER(_Problem)] + [ctypes.c_double] * 4 + [dp, dp]
         lib.orc_lax_friedrichs.restype = ctypes.c_double
         lib.orc_lax_friedrichs.argtypes = [ctypes.POINTER(_Problem)] + [ctypes.c_double] * 6
+        lib.orc_curvature_term.restype = ctypes.c_double
+        lib.orc_curvature_term.argtypes = [ctypes.POINTER(_Problem), dp, ctypes.c_int64,
+                                           ctypes.c_int64]
         lib.orc_rk3_step.restype = ctypes.c_int
         lib.orc_rk3_step.argtypes = [ctypes.POINTER(_Problem), dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.POINTER(_Info)]
@@ -252,6 +255,16 @@ def dissipation(prob: Problem, A, B, C=0.0, D=0.0):
 def lax_friedrichs(prob: Problem, um, up, vm=0.0, vp=0.0, ax=0.0, ay=0.0):
     return _load().orc_lax_friedrichs(ctypes.byref(prob._c), float(um), float(up), float(vm),
                                       float(vp), float(ax), float(ay))
+
+
+def curvature_term(prob: Problem, phi):
+    """N / (1 + |grad phi|^2) at every node, from central differences (Example 3.13's
+    term, without eps; see orc_curvature_term)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    lib = _load()
+    ny, nx = phi.shape
+    return np.array([[lib.orc_curvature_term(ctypes.byref(prob._c), _dptr(phi), i, j)
+                      for i in range(nx)] for j in range(ny)])
 
 
 def rk3_step(prob: Problem, phi, t, t_final, cfl):

@@ -53,7 +53,7 @@
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1, ORC_BC_DIRICHLET = 2 };
 enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3,
-       ORC_H_QUARTIC = 4, ORC_H_CONTROL = 5 };
+       ORC_H_QUARTIC = 4, ORC_H_CONTROL = 5, ORC_H_CURVATURE = 6 };
 enum { ORC_SCHEME_WENO_L = 0, ORC_SCHEME_WENO_JP = 1 };
 
 typedef struct {
@@ -326,7 +326,10 @@ int orc_derivatives(const orc_problem *p, const double *phi, double *um, double 
  *   NORM     s sqrt(u^2 + v^2 + k)        (Example 3.12 with k = 1; level-set motion with k = 0)
  *   QUARTIC  (s^2 - 1)(s^2 - 4) / 4, s = a u + b v + c   (Example 3.8, nonconvex)
  *   CONTROL  sin(y) u + (sin(x) + sign v) v - sin(y)^2 / 2 - (1 - cos x)   (Example 3.11)
- * hp = {a, b, c} or {s, k} (CONTROL has none).  In 1-D v is 0.  (x, y) is the node.
+ *   CURVATURE s sqrt(u^2 + v^2 + k), with the curvature term of Example 3.13 (weight
+ *            eps = hp[2]) added to the operator; see curvature_term()
+ * hp = {a, b, c} or {s, k} or {s, k, eps} (CONTROL has none).  In 1-D v is 0.  (x, y) is
+ * the node.
  * ------------------------------------------------------------------------- */
 static double sign_of(double v)
 {
@@ -356,6 +359,7 @@ double orc_hamiltonian_at(const orc_problem *p, double x, double y, double u, do
     case ORC_H_NEGCOS:
         return -cos(h[0] * u + h[1] * v + h[2]);
     case ORC_H_NORM:
+    case ORC_H_CURVATURE:
         return h[0] * sqrt(u * u + v * v + h[1]);
     default:
         return NAN;
@@ -425,7 +429,8 @@ void orc_dissipation(const orc_problem *p, double A, double B, double C, double 
         *ay = fabs(h[1]) * m;
         return;
     }
-    case ORC_H_NORM: {
+    case ORC_H_NORM:
+    case ORC_H_CURVATURE: {
         /* |H_1| = |s| |u| / sqrt(u^2+v^2+k): largest at the largest |u| and the smallest |v| */
         const double U = fmax(fabs(A), fabs(B));
         const double V = fmax(fabs(C), fabs(D));
@@ -474,7 +479,42 @@ static int held(const orc_problem *p, int64_t k)
     return 0;
 }
 
-/* L(phi) = -H_hat at every node, given alpha (0 at held nodes). */
+/* ---------------------------------------------------------------------------
+ * Example 3.13: phi_t - (1 - eps K) sqrt(phi_x^2 + phi_y^2 + 1) = 0.  K is read as the
+ * mean curvature of the level sets of phi in its sign convention that makes the term
+ * diffusive,
+ *     K = -[(1 + phi_y^2) phi_xx - 2 phi_x phi_y phi_xy + (1 + phi_x^2) phi_yy]
+ *         / (1 + phi_x^2 + phi_y^2)^(3/2),
+ * so that eps K sqrt(1 + |grad phi|^2) = -eps N / (1 + |grad phi|^2) with N the bracket,
+ * and phi_t + H(grad phi) = eps N / (1 + |grad phi|^2), H = -sqrt(|grad phi|^2 + 1).
+ * The paper gives no discretization of the term: second-order central differences of
+ * phi at the node and its eight neighbours (wrapped on a periodic axis; the free nodes
+ * of a Dirichlet axis have them inside the grid).
+ * ------------------------------------------------------------------------- */
+static int64_t wrap_index(int64_t i, int64_t n)
+{
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+double orc_curvature_term(const orc_problem *p, const double *phi, int64_t i, int64_t j)
+{
+    const int64_t nx = p->nx, ny = p->ny;
+    const int64_t im = wrap_index(i - 1, nx), ip = wrap_index(i + 1, nx);
+    const int64_t jm = wrap_index(j - 1, ny), jp = wrap_index(j + 1, ny);
+#define PHI(a, b) phi[(b) * nx + (a)]
+    const double c = PHI(i, j);
+    const double px = (PHI(ip, j) - PHI(im, j)) / (2.0 * p->dx);
+    const double py = (PHI(i, jp) - PHI(i, jm)) / (2.0 * p->dy);
+    const double pxx = (PHI(ip, j) - 2.0 * c + PHI(im, j)) / (p->dx * p->dx);
+    const double pyy = (PHI(i, jp) - 2.0 * c + PHI(i, jm)) / (p->dy * p->dy);
+    const double pxy = (PHI(ip, jp) - PHI(im, jp) - PHI(ip, jm) + PHI(im, jm)) / (4.0 * p->dx * p->dy);
+#undef PHI
+    const double N = (1.0 + py * py) * pxx - 2.0 * px * py * pxy + (1.0 + px * px) * pyy;
+    return N / (1.0 + px * px + py * py);
+}
+
+/* L(phi) = -H_hat at every node, given alpha (0 at held nodes), plus eps times the
+ * curvature term for Example 3.13. */
 static int operator_L(const orc_problem *p, const double *phi, double ax, double ay, double *L,
                       double *um, double *up, double *vm, double *vp)
 {
@@ -486,6 +526,8 @@ static int operator_L(const orc_problem *p, const double *phi, double ax, double
         const double x = p->x0 + (double)(k % p->nx) * p->dx;
         const double y = (p->dim == 2) ? p->y0 + (double)(k / p->nx) * p->dy : 0.0;
         L[k] = held(p, k) ? 0.0 : -orc_lax_friedrichs_at(p, x, y, um[k], up[k], a, b, ax, ay);
+        if (p->ham == ORC_H_CURVATURE && !held(p, k))
+            L[k] += p->hp[2] * orc_curvature_term(p, phi, k % p->nx, k / p->nx);
     }
     return 0;
 }
@@ -501,9 +543,12 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
     double *um = malloc(bytes), *up = malloc(bytes), *vm = malloc(bytes), *vp = malloc(bytes);
     double *L = malloc(bytes), *p0 = malloc(bytes), *p1 = malloc(bytes), *p2 = malloc(bytes);
     int rc = 0;
-    /* a Dirichlet axis needs at least one node beyond its six held layers */
+    /* a Dirichlet axis needs at least one node beyond its six held layers; the curvature
+     * term is 2-D, on periodic or Dirichlet axes, with eps >= 0 */
     if ((p->bc_x == ORC_BC_DIRICHLET && p->nx < 7) ||
-        (p->dim == 2 && p->bc_y == ORC_BC_DIRICHLET && p->ny < 7)) {
+        (p->dim == 2 && p->bc_y == ORC_BC_DIRICHLET && p->ny < 7) ||
+        (p->ham == ORC_H_CURVATURE &&
+         (p->dim != 2 || p->bc_x == ORC_BC_EXTRAP || p->bc_y == ORC_BC_EXTRAP || !(p->hp[2] >= 0.0)))) {
         rc = -1;
         goto out;
     }
@@ -535,7 +580,11 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
     }
     double ax, ay;
     orc_dissipation(p, A, B, C, D, &ax, &ay);
-    const double rate = ax / p->dx + ((p->dim == 2) ? ay / p->dy : 0.0);
+    double rate = ax / p->dx + ((p->dim == 2) ? ay / p->dy : 0.0);
+    /* the curvature term diffuses with a coefficient of at most eps: its explicit limit
+     * enters the rate (a reading; the paper gives no time step for Example 3.13) */
+    if (p->ham == ORC_H_CURVATURE)
+        rate += 2.0 * p->hp[2] * (1.0 / (p->dx * p->dx) + 1.0 / (p->dy * p->dy));
     const double remaining = t_final - t;
     double dt = (rate > 0.0) ? cfl / rate : remaining;
     int last = 0;

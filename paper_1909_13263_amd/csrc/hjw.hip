@@ -469,7 +469,7 @@ hjw_status hjw_set_scheme(hjw_grid* g, int scheme) {
 
 hjw_status hjw_set_hamiltonian(hjw_grid* g, int kind, const double* params, int nparams) {
     if (!g) return fail(HJW_EINVAL, "grid is NULL");
-    if (kind < HJW_H_LINEAR || kind > HJW_H_CONTROL)
+    if (kind < HJW_H_LINEAR || kind > HJW_H_CURVATURE)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", kind);
     if (nparams < 0 || nparams > 4 || (nparams > 0 && !params))
         return fail(HJW_EINVAL, "bad parameter list");
@@ -478,7 +478,13 @@ hjw_status hjw_set_hamiltonian(hjw_grid* g, int kind, const double* params, int 
         if (!std::isfinite(params[k])) return fail(HJW_EINVAL, "non-finite parameter");
         p[k] = params[k];
     }
-    if (kind == HJW_H_NORM && p[1] < 0.0) return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    if ((kind == HJW_H_NORM || kind == HJW_H_CURVATURE) && p[1] < 0.0)
+        return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    if (kind == HJW_H_CURVATURE) {
+        if (g->dim != 2 || g->bcx == HJW_BC_EXTRAP || g->bcy == HJW_BC_EXTRAP)
+            return fail(HJW_EINVAL, "CURVATURE needs a 2-D grid with periodic or Dirichlet axes");
+        if (p[2] < 0.0) return fail(HJW_EINVAL, "CURVATURE needs eps = p[2] >= 0");
+    }
     g->ham = kind;
     for (int k = 0; k < 4; ++k) g->hp[k] = p[k];
     g->ham_set = true;

@@ -145,6 +145,8 @@ struct Emu {
                 for (int t = 0; t < TL::kThreads; ++t)
                     TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data(), pnL.data());
             }
+            for (int t = 0; t < TL::kThreads; ++t)
+                TL::template load_corners<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data());
             // the row threads and the column threads, then the barrier, then the finish
             std::vector<T> vm(size_t(TL::kHalf) * S), vp(size_t(TL::kHalf) * S);
             std::vector<T> vL(TL::kVElems, T(NAN));

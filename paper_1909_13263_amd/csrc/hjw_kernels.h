@@ -219,6 +219,7 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
         if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;
         TL::template load<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL, pnL);
     }
+    TL::template load_corners<STAGE>(tid, a, x0, y0, dt, ax, ay, phiL);
     __syncthreads();
     T vm[S], vp[S];
     const bool rows = tid < TL::kHalf;   // wave-uniform: the first half of the waves march rows
@@ -261,8 +262,15 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     TL::sweep_x(tid, a, phiL, uL);
     __syncthreads();
     Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
-    for (int c = tid; c < kTX1; c += 256)
-        fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], kCenter ? pnL[c] : P(0));
+    if (fin.extended()) {
+        for (int c = tid; c < kTX1; c += 256)
+            fin.template node<true>(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3],
+                                    kCenter ? pnL[c] : P(0));
+    } else {
+        for (int c = tid; c < kTX1; c += 256)
+            fin.template node<false>(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3],
+                                     kCenter ? pnL[c] : P(0));
+    }
     if (STAGE == kStagePre) {
         fold_range<4>(a, int(blockIdx.x), fin.lo_u, fin.hi_u, T(0), T(0), fin.bad);
     } else if (STAGE == kStageLast) {

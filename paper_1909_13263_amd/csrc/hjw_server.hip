@@ -204,13 +204,17 @@ hjw_status validate(const hjw_request& r) {
             r.bc[d] != HJW_BC_DIRICHLET)
             return fail(HJW_EINVAL, "request axis %d: unknown boundary %d", d, r.bc[d]);
     }
-    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_CONTROL)
+    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_CURVATURE)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", r.ham);
     if (r.scheme != HJW_WENO_L && r.scheme != HJW_WENO_JP)
         return fail(HJW_EINVAL, "unknown scheme %d", r.scheme);
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(r.params[k])) return fail(HJW_EINVAL, "non-finite parameter");
-    if (r.ham == HJW_H_NORM && r.params[1] < 0.0) return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    if ((r.ham == HJW_H_NORM || r.ham == HJW_H_CURVATURE) && r.params[1] < 0.0)
+        return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    if (r.ham == HJW_H_CURVATURE &&
+        (r.bc[0] == HJW_BC_EXTRAP || r.bc[1] == HJW_BC_EXTRAP || r.params[2] < 0.0))
+        return fail(HJW_EINVAL, "CURVATURE needs periodic or Dirichlet axes and eps >= 0");
     if (!std::isfinite(r.t_final) || r.t_final < 0.0 || !(r.cfl > 0.0) || !std::isfinite(r.cfl))
         return fail(HJW_EINVAL, "need finite t_final >= 0 and cfl > 0");
     return HJW_OK;

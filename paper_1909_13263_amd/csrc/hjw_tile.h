@@ -53,6 +53,7 @@ constexpr int kHNegcos = 2;
 constexpr int kHNorm = 3;
 constexpr int kHQuartic = 4;
 constexpr int kHControl = 5;
+constexpr int kHCurvature = 6;   // NORM plus the curvature term of Example 3.13
 
 // Stage kinds of one Runge-Kutta step.
 constexpr int kStagePre = 0;    // derivatives of phi^n -> Hbar, Dx, Dy, block ranges
@@ -351,7 +352,8 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
 // H(u, v) at the node (x, y); only the control Hamiltonian of Example 3.11 depends on
 // the position:
 //   LINEAR a u + b v; BURGERS s^2/2; NEGCOS -cos s; QUARTIC (s^2-1)(s^2-4)/4 with
-//   s = a u + b v + c; NORM k0 sqrt(u^2 + v^2 + k1);
+//   s = a u + b v + c; NORM and CURVATURE k0 sqrt(u^2 + v^2 + k1) (the curvature term
+//   is added by the finisher);
 //   CONTROL sin(y) u + (sin(x) + sign v) v - sin(y)^2/2 - (1 - cos x).
 template <typename T>
 __host__ __device__ inline T hamiltonian(int kind, const T* p, T u, T v, T x, T y) {
@@ -442,12 +444,14 @@ __host__ __device__ inline void dissipation(int kind, const double* p, int dim, 
 }
 
 // Advance the step state once the ranges of phi^n's derivatives are known:
-// dt = cfl / (ax/dx + ay/dy), landing exactly on t_final.
+// dt = cfl / (ax/dx + ay/dy) (plus the curvature term's limit), landing exactly on t_final.
 __host__ __device__ inline void plan_step(DevState& s, int kind, const double* p, int dim,
                                           double ihx, double ihy, const double range[4]) {
     double ax, ay;
     dissipation(kind, p, dim, range[0], range[1], range[2], range[3], ax, ay);
-    const double rate = mul_rn(ax, ihx) + (dim == 2 ? mul_rn(ay, ihy) : 0.0);
+    double rate = mul_rn(ax, ihx) + (dim == 2 ? mul_rn(ay, ihy) : 0.0);
+    // the curvature term diffuses with a coefficient of at most eps = p[2]
+    if (kind == kHCurvature) rate += 2.0 * p[2] * (mul_rn(ihx, ihx) + mul_rn(ihy, ihy));
     const double remaining = s.t_final - s.t;
     double dt = rate > 0.0 ? s.cfl / rate : remaining;
     double tn = s.t + dt;
@@ -664,6 +668,19 @@ struct Tile {
         }
     }
 
+    // The curvature term's cross difference needs the four diagonal neighbours of the
+    // tile's corner nodes, which the plus-shaped region leaves out: four threads load
+    // them after the rest of the tile (any boundary; on a Dirichlet axis only held nodes
+    // read them).
+    template <int STAGE>
+    __host__ __device__ static void load_corners(int tid, const StageArgs<T, P>& a, int64_t x0,
+                                                 int64_t y0, double dt, double ax, double ay,
+                                                 P* phiL) {
+        if (a.ham != kHCurvature || tid >= 4) return;
+        const int r = (tid & 1) ? TY + 3 : 2, c = (tid & 2) ? TX + 3 : 2;
+        phiL[r * PW + c] = stage_value<STAGE>(a, x0 + c - 3, y0 + r - 3, dt, ax, ay);
+    }
+
     // Second stage on a tile whose halo lies inside the grid, split around the step
     // plan: gather() stages phi^n of the plus-shaped region in phiL (and of the tile in
     // pnL) and keeps the region's flux records in registers; after dt and the
@@ -792,6 +809,17 @@ struct Tile {
     __host__ __device__ static void finish(int t, bool col_half, const T* uL, const T* vm,
                                            const T* vp, const T* vL, const P* phiL,
                                            const P* pnL, Fin& fin) {
+        fin.tileL = phiL;
+        fin.pw = PW;
+        if (fin.extended())
+            finish_nodes<true>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
+        else
+            finish_nodes<false>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
+    }
+    template <bool EXT, class Fin>
+    __host__ __device__ static void finish_nodes(int t, bool col_half, const T* uL, const T* vm,
+                                                 const T* vp, const T* vL, const P* phiL,
+                                                 const P* pnL, Fin& fin) {
         const int col = t % TX;
         const int seg = t / TX;
 #pragma unroll
@@ -800,8 +828,9 @@ struct Tile {
             const int slot = (seg * kKeep + j) * TX + col;
             const T m = col_half ? vm[j] : vL[slot];
             const T p = col_half ? vp[j] : vL[kVElems / 2 + slot];
-            fin(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col], m, p,
-                phiL[(row + 3) * PW + col + 3], pnL ? pnL[row * TX + col] : P(0));
+            fin.template node<EXT>(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col],
+                                   m, p, phiL[(row + 3) * PW + col + 3],
+                                   pnL ? pnL[row * TX + col] : P(0));
         }
     }
 };
@@ -853,20 +882,56 @@ struct Finisher {
     T lo_u, hi_u, lo_v, hi_v;
     bool bad;
     int dim;
+    const P* tileL = nullptr;   // the stage input on the tile (2-D; curvature term only)
+    int pw = 0;                 // its row pitch
 
     __host__ __device__ Finisher(const StageArgs<T, P>& args, int64_t x0_, int64_t y0_,
                                  double dt_, double ax_, double ay_, int dim_)
         : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), lo_u(T(INFINITY)),
           hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {}
 
+    // Example 3.13's curvature term N / (1 + phi_x^2 + phi_y^2) of the stage input,
+    // N = (1 + phi_y^2) phi_xx - 2 phi_x phi_y phi_xy + (1 + phi_x^2) phi_yy, from central
+    // differences over the node's 3 x 3 neighbourhood (differences of the stored values
+    // taken in the storage precision).
+    __host__ __device__ T curvature_term(int col, int row) const {
+        const P* c = tileL + (row + 3) * pw + (col + 3);
+        const P pc = c[0];
+        const T de = T(c[1] - pc), dw = T(c[-1] - pc);
+        const T dn = T(c[pw] - pc), ds = T(c[-pw] - pc);
+        const T dxy = T((c[pw + 1] - c[pw - 1]) - (c[-pw + 1] - c[-pw - 1]));
+        const T ihx = a.ihxT, ihy = a.ihyT;
+        const T px = T(0.5) * (de - dw) * ihx, py = T(0.5) * (dn - ds) * ihy;
+        const T pxx = (de + dw) * (ihx * ihx), pyy = (dn + ds) * (ihy * ihy);
+        const T pxy = T(0.25) * dxy * (ihx * ihy);
+        const T num = ((T(1) + py * py) * pxx - T(2) * (px * py) * pxy) + (T(1) + px * px) * pyy;
+        return num / ((T(1) + px * px) + py * py);
+    }
+
     __host__ __device__ bool held(int64_t i, int64_t j) const {
         return (a.bcx == kBcDirichlet && (i < 3 || i >= a.nx - 3)) ||
                (dim == 2 && a.bcy == kBcDirichlet && (j < 3 || j >= a.ny - 3));
     }
 
-    // ps: the stage input at the node (phi_1 in the second stage, phi_2 in the third);
-    // pn: phi^n at the node (second and third stages).
+    // Whether a held layer or the curvature term can occur: uniform over the launch, so
+    // callers pick node<true> or node<false> once, outside their loops over nodes, and
+    // the common case carries neither test.
+    __host__ __device__ bool extended() const {
+        return a.bcx == kBcDirichlet ||
+               (dim == 2 && (a.bcy == kBcDirichlet || a.ham == kHCurvature));
+    }
+
     __host__ __device__ void operator()(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
+        if (extended())
+            node<true>(col, row, um, up, vm, vp, ps, pn_);
+        else
+            node<false>(col, row, um, up, vm, vp, ps, pn_);
+    }
+
+    // ps: the stage input at the node (phi_1 in the second stage, phi_2 in the third);
+    // pn: phi^n at the node (second and third stages).  EXT: extended() holds.
+    template <bool EXT>
+    __host__ __device__ void node(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
         const int64_t i = x0 + col, j = y0 + row;
         if (i >= a.nx || j >= a.ny) return;
         const int64_t idx = j * a.nx + i;
@@ -879,7 +944,7 @@ struct Finisher {
             }
             return;
         }
-        const bool hold = held(i, j);
+        const bool hold = EXT && held(i, j);
         if (STAGE == kStagePre && hold) {
             // phi_1 = phi^n - dt (0 - 0) is phi^n exactly
             reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{T(0), T(0), T(0)};
@@ -890,7 +955,9 @@ struct Finisher {
         // node coordinates, for the position-dependent Hamiltonian only
         const T xn = a.ham == kHControl ? T(a.x0 + double(i) * a.dxD) : T(0);
         const T yn = a.ham == kHControl ? T(a.y0 + double(j) * a.dyD) : T(0);
-        const T H = hamiltonian(a.ham, a.hpT, ub, vb, xn, yn);
+        T H = hamiltonian(a.ham, a.hpT, ub, vb, xn, yn);
+        // the curvature term enters the operator as -eps times a part of H
+        if (EXT && dim == 2 && a.ham == kHCurvature) H -= a.hpT[2] * curvature_term(col, row);
         if (STAGE == kStagePre) {
             reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{H, Dx, Dy};
             lo_u = fmin(lo_u, fmin(um, up));
@@ -909,7 +976,7 @@ struct Finisher {
         } else {
             res = (1.0 / 3.0) * pn + (2.0 / 3.0) * (double(ps) - dt * double(R));
         }
-        const P outv = hold ? pn_ : P(res);
+        const P outv = EXT && hold ? pn_ : P(res);
         a.out[idx] = outv;
         if (!finite_t(outv)) bad = true;
     }

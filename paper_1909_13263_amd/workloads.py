@@ -33,7 +33,7 @@ from dataclasses import dataclass
 import numpy as np
 
 BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL = 0, 1, 2, 3, 4, 5
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE = 0, 1, 2, 3, 4, 5, 6
 CIRCLE_SEED = 13263
 SERVE_SEED = 1909
 
@@ -129,6 +129,14 @@ def ex312_eikonal(n=80, t_final=0.6):
                    (1.0, 1.0), t_final)
 
 
+def ex313_curvature(n=60, eps=0.1, t_final=0.6):
+    """Example 3.13: phi_t - (1 - eps K) sqrt(|grad phi|^2 + 1) = 0 on the periodic unit
+    square, eps = 0 (convection only) or 0.1.  The paper gives no final time; 0.6 is
+    Example 3.12's, whose domain and data (up to sign and shift) it shares."""
+    return Problem("ex313_curvature", (n, n), (0.0, 0.0), (1.0, 1.0), BC_PERIODIC,
+                   H_CURVATURE, (-1.0, 1.0, float(eps)), t_final)
+
+
 def figure_examples():
     """The figure-only examples of Section 3 at the paper's grid sizes and times (with
     the 1-D Burgers and -cos runs past the kink time, Examples 3.6 and 3.7, and the 2-D
@@ -136,7 +144,7 @@ def figure_examples():
     return [ex35_linear(100, 2.0), ex35_linear(100, 8.0), burgers1d(40, 3.5 / math.pi**2),
             negcos1d(80, 1.5 / math.pi**2), ex38_quartic(100, 1.0),
             burgers2d(40, 1.5 / math.pi**2), ex310_sin2d(80, 1.0), ex311_control(60, 1.0),
-            ex312_eikonal(80, 0.6)]
+            ex312_eikonal(80, 0.6), ex313_curvature(60, 0.0), ex313_curvature(60, 0.1)]
 
 
 def ex35_phi0(x):
@@ -181,6 +189,9 @@ def initial_data(p: Problem) -> np.ndarray:
     if p.name == "ex312_eikonal":
         x, y = p.coords(0), p.coords(1)
         return 0.25 * (np.cos(2 * math.pi * x)[None, :] - 1) * (np.cos(2 * math.pi * y)[:, None] - 1) - 1
+    if p.name == "ex313_curvature":
+        x, y = p.coords(0), p.coords(1)
+        return 1 - 0.25 * (np.cos(2 * math.pi * x)[None, :] - 1) * (np.cos(2 * math.pi * y)[:, None] - 1)
     if p.name in ("burgers2d", "negcos2d"):
         x = p.coords(0)
         y = p.coords(1)

@@ -53,6 +53,22 @@ def test_create_rejects_bad_arguments(args, msg):
     assert not h.value
 
 
+@pytest.mark.parametrize("dim,bc,params,ok", [
+    (2, [0, 0], [-1.0, 1.0, 0.1], True), (2, [2, 0], [-1.0, 1.0, 0.0], True),
+    (2, [1, 0], [-1.0, 1.0, 0.1], False), (2, [0, 1], [-1.0, 1.0, 0.1], False),
+    (1, [0], [-1.0, 1.0, 0.1], False), (2, [0, 0], [-1.0, 1.0, -0.1], False),
+    (2, [0, 0], [-1.0, -1.0, 0.1], False)])
+def test_curvature_hamiltonian_validation(dim, bc, params, ok):
+    rc, h = _create(dim, [16] * dim, [0] * dim, [1] * dim, bc, hjw.FP64)
+    assert rc == 0
+    arr = (ctypes.c_double * 3)(*params)
+    rc = hjw.lib().hjw_set_hamiltonian(h, hjw.H_CURVATURE, arr, 3)
+    assert rc == (hjw.OK if ok else hjw.EINVAL)
+    if not ok:
+        assert "CURVATURE" in hjw.lib().hjw_last_error().decode() or "NORM" in hjw.lib().hjw_last_error().decode()
+    hjw.lib().hjw_grid_destroy(h)
+
+
 @pytest.mark.parametrize("bc", [[2, 2], [2, 0], [1, 2]])
 def test_create_accepts_dirichlet(bc):
     rc, h = _create(2, [16, 9], [-1, -1], [1, 1], bc, hjw.FP64)

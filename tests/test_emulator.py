@@ -126,7 +126,7 @@ def _origin(pr):
     return tuple(pr.coords(a)[0] for a in range(pr.dim)) + (0.0,) * (2 - pr.dim)
 
 
-@pytest.mark.parametrize("name", ["ex35", "ex38", "ex310", "ex311", "ex312"])
+@pytest.mark.parametrize("name", ["ex35", "ex38", "ex310", "ex311", "ex312", "ex313"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_emulated_figure_examples_match_oracle(name, prec, tile_rows):
     """The Hamiltonians of Examples 3.5 and 3.8-3.12 (the quartic, the position-dependent
@@ -134,7 +134,8 @@ def test_emulated_figure_examples_match_oracle(name, prec, tile_rows):
     from a state part way along the solve."""
     pr = {"ex35": lambda: W.ex35_linear(160, 0.5), "ex38": lambda: W.ex38_quartic(100, 0.2),
           "ex310": lambda: W.ex310_sin2d(70, 0.2), "ex311": lambda: W.ex311_control(66, 0.2),
-          "ex312": lambda: W.ex312_eikonal(72, 0.2)}[name]()
+          "ex312": lambda: W.ex312_eikonal(72, 0.2),
+          "ex313": lambda: W.ex313_curvature(66, 0.1, 0.05)}[name]()
     x0, y0 = _origin(pr)
     EM.set_origin(x0, y0)
     try:
@@ -174,3 +175,22 @@ def test_emulated_dirichlet_step_matches_oracle(shape, bc, prec, tile_rows):
         held[:3, :] = held[-3:, :] = True
     p_cast = phi if prec < 2 else phi.astype(np.float32).astype(np.float64)
     assert np.array_equal(got[held], p_cast[held])
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (33, 65), (100, 200), (135, 260)])
+@pytest.mark.parametrize("bc", [(0, 0), (2, 2), (0, 2)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_curvature_step_matches_oracle(shape, bc, prec, tile_rows):
+    """Example 3.13's term in the tile code: its 3 x 3 stencil reaches the four corner
+    cells beyond the plus-shaped region (NaN in the emulated LDS unless loaded), on
+    ragged tiles and across periodic wraps."""
+    h = (1.0 / shape[1], 1.0 / shape[0])
+    params = (-1.0, 1.0, 0.05)
+    phi = 0.05 * W.random_smooth_periodic(shape, seed=sum(shape) + 11)
+    prob = O.Problem(shape, h, O.H_CURVATURE, params, bc)
+    ref, info = O.rk3_step(prob, phi, 0.0, 1.0, 0.5)
+    rc, got, ei = EM.rk3_step(phi, h, O.H_CURVATURE, params, 0.0, 1.0, 0.5, bc, prec)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    tol = {0: 1e-14, 1: 1e-7, 2: 1e-6}[prec]
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()

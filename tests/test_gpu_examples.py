@@ -167,3 +167,44 @@ def test_dirichlet_requests_through_the_server():
         g.close()
         assert results[sid].status == hjw.OK
         assert np.array_equal(results[sid].phi, ref), pr.name
+
+
+# --------------------------------------------------------------------------- curvature
+CURV_CASES = [((135, 200), (0, 0)), ((100, 130), (2, 2)), ((70, 260), (0, 2))]
+
+
+@pytest.mark.parametrize("shape,bc", CURV_CASES, ids=[f"{s}-{b}" for s, b in CURV_CASES])
+def test_curvature_whole_solves(shape, bc):
+    """Example 3.13's term on ragged multi-tile grids (the tile corners it reads, periodic
+    wraps, held layers): FP64 within 1e-12 of the oracle, the FP32 paths within bounds."""
+    lo, hi = (0.0, 0.0), (1.0, 1.0)
+    params = (-1.0, 1.0, 0.02)
+    h = (1.0 / shape[1], 1.0 / shape[0])
+    phi0 = 0.05 * W.random_smooth_periodic(shape, seed=sum(shape) + 11)
+    prob = O.Problem(shape, h, O.H_CURVATURE, params, bc)
+    ref, info = O.step_to(prob, phi0, 0.01, 0.5)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 2e-6), (FP32, 3e-5)]:
+        g = hjw.Grid(shape, lo, hi, bc, prec)
+        g.set_hamiltonian(hjw.H_CURVATURE, params)
+        g.set_phi(phi0)
+        gi = g.step_to(0.01, 0.5)
+        phi = g.get_phi()
+        g.close()
+        assert abs(gi.steps - info.steps) <= (0 if prec == FP64 else 1)
+        err = float(np.abs(phi - ref).max() / np.abs(ref).max())
+        print(f"curvature {shape} bc={bc} prec={prec} steps={gi.steps} rel={err:.3e}", flush=True)
+        assert err <= tol
+
+
+def test_curvature_full_size_steps():
+    """1024^2 in the benchmark's launch configuration (plan launch off below 2048 tiles,
+    S = 8 tiles): three steps against the oracle."""
+    pr = W.ex313_curvature(1024, 0.1, 1.0)
+    ref, _ = O.step_to(_oracle(pr), pr.phi0(), 1.0, pr.cfl, max_steps=3)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 1e-6)]:
+        g = hjw.grid_for(pr, prec)
+        g.set_phi(pr.phi0())
+        g.step_to(1.0, pr.cfl, max_steps=3)
+        err = float(np.abs(g.get_phi() - ref).max() / np.abs(ref).max())
+        g.close()
+        assert err <= tol, (prec, err)

@@ -195,3 +195,79 @@ def test_example310_dirichlet_corners_and_symmetry():
     assert np.isfinite(phi).all()
     assert np.abs(phi + phi.T).max() <= 1e-13
     assert np.abs(phi + phi.T).max() <= 1e-13
+
+
+# --------------------------------------------------------------------------- curvature
+def test_curvature_term_is_the_mean_curvature_of_a_sphere():
+    """On the upper half of a sphere of radius R the graph's mean-curvature expression
+    N / (1 + |grad phi|^2)^(3/2) is -2/R everywhere, so the term N / (1 + |grad phi|^2) is
+    -(2/R) sqrt(1 + |grad phi|^2).  The central differences reach it at second order.  The
+    printed (1 + phi_y)^2 in place of 1 + phi_y^2, or a wrong sign on the cross term,
+    would miss it by O(1)."""
+    R = 1.0
+    errs = []
+    for n in (40, 80, 160):
+        h = 1.0 / n
+        x = -0.5 + np.arange(n) * h
+        X, Y = np.meshgrid(x, x)
+        phi = np.sqrt(R * R - X * X - Y * Y)
+        prob = O.Problem((n, n), (h, h), O.H_CURVATURE, (-1.0, 1.0, 0.1), O.BC_DIRICHLET)
+        g = O.curvature_term(prob, phi)
+        ex = -2.0 / R * np.sqrt(1 + (X * X + Y * Y) / (phi * phi))
+        errs.append(float(np.abs(g - ex)[1:-1, 1:-1].max()))
+    slopes = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert errs[-1] < 1e-4 and all(1.9 < s < 2.1 for s in slopes), (errs, slopes)
+
+
+def test_curvature_flow_damps_a_small_mode_at_the_discrete_heat_rate():
+    """With H = 0 (p[0] = 0) and a small amplitude the term is eps times the five-point
+    Laplacian (the slopes enter at second order in the amplitude), whose eigenvector
+    sin(2 pi k x) sin(2 pi k y) has the eigenvalue -(8/h^2) sin^2(pi k h).  dt then comes
+    from the curvature limit alone, dt = cfl / (4 eps / h^2), and every RK3 step multiplies
+    the mode by 1 + z + z^2/2 + z^3/6 with z = -eps lambda dt = -2 cfl sin^2(pi k h).  The
+    sign (the term damps), its weight and the time-step rule are all in the factor."""
+    n, k, eps, cfl, amp = 32, 4, 0.1, 0.5, 1e-6
+    h = 1.0 / n
+    x = np.arange(n) * h
+    mode = np.sin(2 * math.pi * k * x)[None, :] * np.sin(2 * math.pi * k * x)[:, None]
+    prob = O.Problem((n, n), (h, h), O.H_CURVATURE, (0.0, 1.0, eps))
+    phi, info = O.step_to(prob, amp * mode, 1.0, cfl, max_steps=40)
+    assert info.last_dt == pytest.approx(cfl / (4 * eps / h**2), rel=1e-15)
+    z = -2 * cfl * math.sin(math.pi * k * h) ** 2
+    g = 1 + z + z * z / 2 + z ** 3 / 6
+    assert np.abs(phi - amp * g ** 40 * mode).max() <= 1e-9 * amp
+    assert g ** 40 < 0.01                     # the mode has decayed substantially
+
+
+def test_curvature_with_zero_weight_is_the_norm_hamiltonian():
+    pr = W.ex313_curvature(40, 0.0, 0.2)
+    a, ia = O.step_to(_problem(pr), pr.phi0(), pr.t_final, pr.cfl)
+    norm = O.Problem(pr.shape, pr.spacing, O.H_NORM, (-1.0, 1.0))
+    b, ib = O.step_to(norm, pr.phi0(), pr.t_final, pr.cfl)
+    assert ia.steps == ib.steps and np.array_equal(a, b)
+
+
+def test_example313_symmetries_and_smoothing():
+    """phi0 and both terms are symmetric under x <-> y and x -> 1 - x on the periodic grid:
+    the solution keeps both.  The curvature term narrows the solution's range."""
+    sols = {}
+    for eps in (0.0, 0.1):
+        pr = W.ex313_curvature(60, eps)
+        phi, _ = O.step_to(_problem(pr), pr.phi0(), pr.t_final, pr.cfl)
+        n = pr.shape[0]
+        assert np.abs(phi - phi.T).max() <= 1e-13
+        refl = phi[:, (-np.arange(n)) % n]
+        assert np.abs(phi - refl).max() <= 1e-12
+        sols[eps] = phi
+    assert np.ptp(sols[0.1]) < 0.5 * np.ptp(sols[0.0])
+
+
+def test_curvature_rejects_unsupported_grids():
+    phi = np.zeros((16, 16))
+    for bc in [(O.BC_EXTRAP, O.BC_PERIODIC), (O.BC_PERIODIC, O.BC_EXTRAP)]:
+        prob = O.Problem((16, 16), (0.1, 0.1), O.H_CURVATURE, (-1.0, 1.0, 0.1), bc)
+        with pytest.raises(FloatingPointError):
+            O.rk3_step(prob, phi, 0.0, 1.0, 0.5)
+    prob = O.Problem((16, 16), (0.1, 0.1), O.H_CURVATURE, (-1.0, 1.0, -0.1))
+    with pytest.raises(FloatingPointError):
+        O.rk3_step(prob, phi, 0.0, 1.0, 0.5)
