@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--tile-rows", type=int, default=0, help="16 or 32 (0: library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served stream")
     ap.add_argument("--no-jp", action="store_true", help="skip the WENO-JP comparison solve")
+    ap.add_argument("--no-families", action="store_true",
+                    help="skip the kernel times of the other Hamiltonians and boundaries")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the FP32-vs-FP64 error of the full-size configurations")
     ap.add_argument("--serve-requests", type=int, default=2048)
@@ -266,6 +268,38 @@ def beyond_mall(hjw, W, steps=3):
             "sustained_frac": rate * step_bytes / 1e9 / HBM_PEAK_GBS}
 
 
+def families(hjw, W, n):
+    """Stage-kernel throughput of every Hamiltonian family and boundary the solver has, on
+    an n x n grid with the FP32 stencil in the benchmark's launch configuration: each stage
+    kernel launched back to back between HIP events.  Node-stages/s = n^2 * 3 / (pre + mid
+    + last)."""
+    import dataclasses
+    cases = [
+        ("burgers, periodic (Ex 3.3)", W.burgers2d(n), None),
+        ("-cos, periodic (Ex 3.4)", W.negcos2d(n), None),
+        ("quartic, periodic (Ex 3.8 in 2-D)",
+         dataclasses.replace(W.burgers2d(n), ham=W.H_QUARTIC, params=(1.0, 1.0, 0.0)), None),
+        ("sin, Dirichlet (Ex 3.10)", W.ex310_sin2d(n), None),
+        ("control, periodic (Ex 3.11)", W.ex311_control(n),
+         W.random_smooth_periodic((n, n), seed=3)),
+        ("sqrt form, periodic (Ex 3.12)", W.ex312_eikonal(n), None),
+        ("curvature eps=0.1, periodic (Ex 3.13)", W.ex313_curvature(n, 0.1), None),
+        ("norm, extrapolated (level set)", W.levelset2d(n), None),
+    ]
+    out = {}
+    base = None
+    for label, pr, phi in cases:
+        g = hjw.grid_for(pr, hjw.FP32_MIXED)
+        g.set_phi(pr.phi0() if phi is None else phi)
+        t = g.time_kernels(reps=50)
+        g.close()
+        total = t["pre"] + t["plan"] + t["mid"] + t["last"]
+        rate = pr.cells * 3 / (total * 1e-3)
+        base = base or rate
+        out[label] = {"kernel_ms": t, "node_stages_per_s": rate, "vs_burgers": rate / base}
+    return out
+
+
 def served_stream(args, hjw):
     """The served stream: Poisson arrivals of mixed solves at a fraction of the measured
     saturation rate, continuous batching on one pool; p50/p99 latency and throughput."""
@@ -393,6 +427,8 @@ def main():
                            "ms_per_step": 1e3 * wall / args.steps, "rk_steps": info.steps,
                            "kernel_ms": times,
                            "time_ratio_jp_over_l": (1e3 * wall / args.steps) / main_res["ms_per_solve"]}
+    if not args.no_families:
+        line["families"] = families(hjw, W, args.n)
     if not args.no_accuracy:
         line["fp32_error_vs_fp64"] = accuracy(hjw)
         line["beyond_infinity_cache"] = beyond_mall(hjw, W)

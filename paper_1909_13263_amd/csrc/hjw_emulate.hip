@@ -137,10 +137,9 @@ struct Emu {
             if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
                 // the kernel's split second stage: gather, plan, then phi_1 in place
                 std::vector<typename TL::Gathered> gth(TL::kThreads);
+                for (int t = 0; t < TL::kThreads; ++t) TL::gather(t, a, x0, y0, gth[t]);
                 for (int t = 0; t < TL::kThreads; ++t)
-                    TL::gather(t, a, x0, y0, phiL.data(), pnL.data(), gth[t]);
-                for (int t = 0; t < TL::kThreads; ++t)
-                    TL::make_phi1(t, a, dt, ax, ay, phiL.data(), gth[t]);
+                    TL::make_phi1(t, a, dt, ax, ay, phiL.data(), pnL.data(), gth[t]);
             } else {
                 for (int t = 0; t < TL::kThreads; ++t)
                     TL::template load<STAGE>(t, a, x0, y0, dt, ax, ay, phiL.data(), pnL.data());

@@ -107,18 +107,57 @@ __device__ inline void fold_range(const StageArgs<T, P>& a, int bid, T lu, T hu,
 // record st[par] (read-only during this launch); workgroup 0 publishes the result in
 // st[par ^ 1].  Returns whether the step is taken; dt and the dissipation go to the
 // references.
+// The plan's inputs: read first (plan_issue), used later (plan_finish), so that a
+// caller can issue its own loads in between and their latencies overlap.  With the
+// plan published by its own launch (plan_ready) every thread reads the record's
+// outcome; otherwise the first wave reads the range slots and thread 0 the record.
+struct PlanIn {
+    DevState s;                   // the step's record (first wave)
+    unsigned long long key[4];    // one range slot per lane of the first wave
+    unsigned int bad;
+    int ready_active;             // the published outcome (plan_ready), kept apart from s
+    double ready_dt, ready_ax, ready_ay;   // so that no value merges the two paths
+};
+
 template <typename T, typename P>
-__device__ inline bool plan_in_block(const StageArgs<T, P>& a, int bid, double& dt, double& ax,
-                                     double& ay) {
-    __shared__ DevState s_plan;
+__device__ inline void plan_issue(const StageArgs<T, P>& a, PlanIn& in) {
+    if (a.plan_ready) {
+        const DevState& n = a.st[a.par ^ 1];
+        in.ready_active = n.active;
+        in.ready_dt = n.dt;
+        in.ready_ax = n.alpha_x;
+        in.ready_ay = n.alpha_y;
+        return;
+    }
     if (threadIdx.x < 64) {
         const RangeSlots* sl = static_cast<const RangeSlots*>(a.slots);
         const int k = threadIdx.x;
-        DevState s;
-        if (k == 0) s = a.st[a.par];   // issued with the slot loads: one memory round trip
-        double r0 = key_value(sl->key[0][k]), r1 = key_value(sl->key[1][k]);
-        double r2 = key_value(sl->key[2][k]), r3 = key_value(sl->key[3][k]);
-        unsigned int b = sl->bad[k];
+        // every lane reads the record (one address): no branch whose result must be
+        // copied, which would wait for the loads here
+        in.s = a.st[a.par];
+        for (int q = 0; q < 4; ++q) in.key[q] = sl->key[q][k];
+        in.bad = sl->bad[k];
+    }
+}
+
+template <typename T, typename P>
+__device__ inline bool plan_finish(const StageArgs<T, P>& a, int bid, const PlanIn& in,
+                                   double& dt, double& ax, double& ay) {
+    if (a.plan_ready) {
+        dt = in.ready_dt;
+        ax = in.ready_ax;
+        ay = in.ready_ay;
+        return in.ready_active != 0;
+    }
+    __shared__ DevState s_plan;
+    if (threadIdx.x < 64) {
+        DevState s = in.s;
+        double r0 = key_value(in.key[0]), r1 = key_value(in.key[1]);
+        double r2 = key_value(in.key[2]), r3 = key_value(in.key[3]);
+        unsigned int b = in.bad;
+        // an empty fence: the test of b below cannot be moved up to the load of b (it
+        // would wait there for the loads a caller issues between plan_issue and here)
+        asm volatile("" : "+v"(b));
         r0 = wave_min(r0);
         r1 = wave_max(r1);
         r2 = wave_min(r2);
@@ -146,6 +185,14 @@ __device__ inline bool plan_in_block(const StageArgs<T, P>& a, int bid, double& 
     ax = s_plan.alpha_x;
     ay = s_plan.alpha_y;
     return s_plan.active != 0;
+}
+
+template <typename T, typename P>
+__device__ inline bool plan_in_block(const StageArgs<T, P>& a, int bid, double& dt, double& ax,
+                                     double& ay) {
+    PlanIn in;
+    plan_issue(a, in);
+    return plan_finish(a, bid, in, dt, ax, ay);
 }
 
 // Third stage, workgroup 0: empty the slots for the next step's first stage.
@@ -209,11 +256,15 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     const int tid = threadIdx.x;
     double dt, ax, ay;
     if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
-        // issue the tile's loads before the step plan so that their latencies overlap
+        // the plan's loads, then the tile's, then the plan: the plan waits only for its
+        // own loads (they were issued first) while the tile's are still in flight
+        PlanIn pin;
+        plan_issue(a, pin);
         typename TL::Gathered gth;
-        TL::gather(tid, a, x0, y0, phiL, pnL, gth);
-        if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;   // uniform over the workgroup
-        TL::make_phi1(tid, a, dt, ax, ay, phiL, gth);
+        TL::gather(tid, a, x0, y0, gth);
+        dt = ax = ay = 0.0;
+        if (!plan_finish(a, bid, pin, dt, ax, ay)) return;   // uniform over the workgroup
+        TL::make_phi1(tid, a, dt, ax, ay, phiL, pnL, gth);
     } else {
         // a step past its end returns before loading anything
         if (!stage_entry<STAGE>(a, bid, dt, ax, ay)) return;
@@ -283,6 +334,7 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
 template <typename T, typename P>
 __global__ __launch_bounds__(64) void k_plan(StageArgs<T, P> a) {
     double dt, ax, ay;
+    a.plan_ready = 0;   // the second stage's arguments say the plan is published: by this
     (void)plan_in_block(a, 0, dt, ax, ay);
 }
 

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(64) void k_plan_batch(const StageArgs<T, P>* table,
     if (int(blockIdx.x) >= *ngrids) return;
     StageArgs<T, P> a = table[blockIdx.x];
     a.par ^= flip;
+    a.plan_ready = 0;   // this launch is the one that publishes the plan
     double dt, ax, ay;
     (void)plan_in_block(a, 0, dt, ax, ay);
 }

@@ -513,9 +513,10 @@ __host__ __device__ inline P node_value(const StageArgs<T, P>& a, int64_t idx, d
                                         double ax, double ay) {
     if (STAGE == kStageMid) {
         // phi_1 = phi^n + dt L(phi^n), L = -(Hbar - (ax Dx + ay Dy))
+        // f.dy and ay are 0 on a 1-D grid, so no test of the dimension: a load under such a
+        // test is issued late and waited for at once, one memory round trip per node
         const Flux3<T> f = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
-        const double ry = a.dim == 2 ? mul_rn(ay, double(f.dy)) : 0.0;
-        const double r = double(f.h) - (mul_rn(ax, double(f.dx)) + ry);
+        const double r = double(f.h) - (mul_rn(ax, double(f.dx)) + mul_rn(ay, double(f.dy)));
         return P(double(a.phi_n[idx]) - dt * r);
     } else if (STAGE == kStageLast) {
         return a.phi_s[idx];
@@ -682,13 +683,14 @@ struct Tile {
     }
 
     // Second stage on a tile whose halo lies inside the grid, split around the step
-    // plan: gather() stages phi^n of the plus-shaped region in phiL (and of the tile in
-    // pnL) and keeps the region's flux records in registers; after dt and the
-    // dissipation are known, make_phi1() turns phiL into phi_1 in place, with the same
-    // arithmetic as node_value().  Element e maps to the same node in both calls.
+    // plan: gather() loads phi^n and the flux records of the plus-shaped region into
+    // registers; after dt and the dissipation are known, make_phi1() writes phi_1 of the
+    // region to phiL (and phi^n of the tile to pnL), with the same arithmetic as
+    // node_value().  Element e maps to the same node in both calls.
     static constexpr int kPlusElems = TY * TX + TY * 6 + 6 * TX;
     static constexpr int kPerThread = (kPlusElems + kThreads - 1) / kThreads;
     struct Gathered {
+        P pn[kPerThread];
         Flux3<T> f[kPerThread];
     };
     __host__ __device__ static void plus_node(int e, int& r, int& c) {
@@ -710,34 +712,25 @@ struct Tile {
     __host__ __device__ static bool inside(const StageArgs<T, P>& a, int64_t x0, int64_t y0) {
         return x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx && y0 + TY + 3 <= a.ny;
     }
+    // Loads only, into registers (the idle threads of the last round load a valid
+    // element): nothing here waits for them, so the step plan's loads, issued before,
+    // and these overlap.
     __host__ __device__ static void gather(int tid, const StageArgs<T, P>& a, int64_t x0,
-                                           int64_t y0, P* phiL, P* pnL, Gathered& g) {
+                                           int64_t y0, Gathered& g) {
         const int64_t base = (y0 - 3) * a.nx + (x0 - 3);
-        // every load first (the idle threads of the last round load a valid element),
-        // then the LDS writes
-        P pn[kPerThread];
 #pragma unroll
         for (int j = 0; j < kPerThread; ++j) {
             const int e = tid + j * kThreads;
             int r, c;
             plus_node(e < kPlusElems ? e : kPlusElems - 1, r, c);
             const int64_t idx = base + r * a.nx + c;
-            pn[j] = a.phi_n[idx];
+            g.pn[j] = a.phi_n[idx];
             g.f[j] = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
         }
-#pragma unroll
-        for (int j = 0; j < kPerThread; ++j) {
-            const int e = tid + j * kThreads;
-            if (e < kPlusElems) {
-                int r, c;
-                plus_node(e, r, c);
-                phiL[r * PW + c] = pn[j];
-                if (e < TY * TX) pnL[e] = pn[j];
-            }
-        }
     }
+    // phi_1 of the plus-shaped region into phiL and phi^n of the tile into pnL.
     __host__ __device__ static void make_phi1(int tid, const StageArgs<T, P>& a, double dt,
-                                              double ax, double ay, P* phiL,
+                                              double ax, double ay, P* phiL, P* pnL,
                                               const Gathered& g) {
 #pragma unroll
         for (int j = 0; j < kPerThread; ++j) {
@@ -746,9 +739,9 @@ struct Tile {
                 int r, c;
                 plus_node(e, r, c);
                 const Flux3<T> f = g.f[j];
-                const double ry = a.dim == 2 ? mul_rn(ay, double(f.dy)) : 0.0;
-                const double rr = double(f.h) - (mul_rn(ax, double(f.dx)) + ry);
-                phiL[r * PW + c] = P(double(phiL[r * PW + c]) - dt * rr);
+                const double rr = double(f.h) - (mul_rn(ax, double(f.dx)) + mul_rn(ay, double(f.dy)));
+                phiL[r * PW + c] = P(double(g.pn[j]) - dt * rr);
+                if (e < TY * TX) pnL[e] = g.pn[j];
             }
         }
     }
