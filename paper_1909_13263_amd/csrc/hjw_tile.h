@@ -534,9 +534,11 @@ __host__ __device__ inline int64_t resolve(int64_t i, int64_t n, int bc, int& gh
     side = 0;
     if (i >= 0 && i < n) return i;
     if (bc == kBcPeriodic) {
-        // 32-bit remainder: axes hold at most 2^30 nodes and i lies within a tile of them
-        const int r = int(i) % int(n);
-        return r < 0 ? int64_t(r) + n : int64_t(r);
+        // one wrap reaches every node a real node's stencil needs (they lie within 3 of
+        // the grid, and n >= 8); nodes further out belong to the unused part of a partial
+        // tile and are clamped
+        const int64_t r = i < 0 ? i + n : i - n;
+        return r < 0 ? 0 : (r >= n ? n - 1 : r);
     }
     if (i < 0) {
         ghost = int(-i);
@@ -633,6 +635,27 @@ struct Tile {
                 const int64_t idx = base + r * a.nx + c;
                 val[j] = node_value<STAGE>(a, idx, dt, ax, ay);
                 if (kCenter && j * kThreads < TY * TX) cen[j] = a.phi_n[idx];
+            }
+        } else if (a.bcx == kBcPeriodic && a.bcy == kBcPeriodic) {
+            // every halo index wraps to one node: one value per element
+            int64_t i0[kPerThread];
+#pragma unroll
+            for (int j = 0; j < kPerThread; ++j) {
+                int r, c;
+                plus_node(element(j), r, c);
+                int64_t i1;
+                int g;
+                ghost_pair(a, x0 + c - 3, y0 + r - 3, i0[j], i1, g);
+            }
+#pragma unroll
+            for (int j = 0; j < kPerThread; ++j) {
+                val[j] = node_value<STAGE>(a, i0[j], dt, ax, ay);
+                if (kCenter && j * kThreads < TY * TX) {
+                    const int e = element(j);
+                    const int64_t i = x0 + (e % TX), jj = y0 + (e / TX);
+                    const int64_t ic = i < a.nx ? i : a.nx - 1, jc = jj < a.ny ? jj : a.ny - 1;
+                    cen[j] = a.phi_n[jc * a.nx + ic];
+                }
             }
         } else {
             int64_t i0[kPerThread], i1[kPerThread];
