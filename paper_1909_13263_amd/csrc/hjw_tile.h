@@ -638,14 +638,19 @@ struct Tile {
             }
         } else if (a.bcx == kBcPeriodic && a.bcy == kBcPeriodic) {
             // every halo index wraps to one node: one value per element
+            const bool full = x0 + TX <= a.nx && y0 + TY <= a.ny;
             int64_t i0[kPerThread];
 #pragma unroll
             for (int j = 0; j < kPerThread; ++j) {
-                int r, c;
-                plus_node(element(j), r, c);
-                int64_t i1;
-                int g;
-                ghost_pair(a, x0 + c - 3, y0 + r - 3, i0[j], i1, g);
+                if (own_round(j) && full) {
+                    i0[j] = own_index(tid + j * kThreads, a, x0, y0);
+                } else {
+                    int r, c;
+                    plus_node(element(j), r, c);
+                    int64_t i1;
+                    int g;
+                    ghost_pair(a, x0 + c - 3, y0 + r - 3, i0[j], i1, g);
+                }
             }
 #pragma unroll
             for (int j = 0; j < kPerThread; ++j) {
@@ -658,13 +663,19 @@ struct Tile {
                 }
             }
         } else {
+            const bool full = x0 + TX <= a.nx && y0 + TY <= a.ny;
             int64_t i0[kPerThread], i1[kPerThread];
             int g[kPerThread];
 #pragma unroll
             for (int j = 0; j < kPerThread; ++j) {
-                int r, c;
-                plus_node(element(j), r, c);
-                ghost_pair(a, x0 + c - 3, y0 + r - 3, i0[j], i1[j], g[j]);
+                if (own_round(j) && full) {
+                    i0[j] = i1[j] = own_index(tid + j * kThreads, a, x0, y0);
+                    g[j] = 0;
+                } else {
+                    int r, c;
+                    plus_node(element(j), r, c);
+                    ghost_pair(a, x0 + c - 3, y0 + r - 3, i0[j], i1[j], g[j]);
+                }
             }
 #pragma unroll
             for (int j = 0; j < kPerThread; ++j) {
@@ -731,6 +742,16 @@ struct Tile {
             c = f % TX + 3;
             r = k < 3 ? k : TY + k;
         }
+    }
+    // Rounds of the load whose elements are all the tile's own nodes (plus_node maps
+    // them first): on a tile that is not partial these lie inside the grid, so an edge
+    // tile indexes them directly and resolves only its halo through the boundary.
+    __host__ __device__ static constexpr bool own_round(int j) {
+        return (j + 1) * kThreads <= TY * TX;
+    }
+    __host__ __device__ static int64_t own_index(int e, const StageArgs<T, P>& a, int64_t x0,
+                                                 int64_t y0) {
+        return (y0 + e / TX) * a.nx + (x0 + e % TX);
     }
     __host__ __device__ static bool inside(const StageArgs<T, P>& a, int64_t x0, int64_t y0) {
         return x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx && y0 + TY + 3 <= a.ny;
