@@ -105,12 +105,12 @@ __device__ inline void fold_range(const StageArgs<T, P>& a, int bid, T lu, T hu,
 
 // Second stage: every workgroup reduces the slots and plans the step from the step
 // record st[par] (read-only during this launch); workgroup 0 publishes the result in
-// st[par ^ 1].  Returns whether the step is taken; dt and the dissipation go to the
-// references.
-// The plan's inputs: read first (plan_issue), used later (plan_finish), so that a
-// caller can issue its own loads in between and their latencies overlap.  With the
+// st[par ^ 1].  plan_finish returns whether the step is taken; dt and the dissipation
+// go to the references.
+// The plan's inputs are read first (plan_issue) and used later (plan_finish), so that
+// a caller can issue its own loads in between and their latencies overlap.  With the
 // plan published by its own launch (plan_ready) every thread reads the record's
-// outcome; otherwise the first wave reads the range slots and thread 0 the record.
+// outcome; otherwise the first wave reads the range slots and the record.
 struct PlanIn {
     DevState s;                   // the step's record (first wave)
     unsigned long long key[4];    // one range slot per lane of the first wave
