@@ -194,3 +194,27 @@ def test_emulated_curvature_step_matches_oracle(shape, bc, prec, tile_rows):
     assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
     tol = {0: 1e-14, 1: 1e-7, 2: 1e-6}[prec]
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+# --------------------------------------------------------------------------- random sweep
+@pytest.mark.parametrize("seed", range(40))
+def test_emulated_random_configurations_match_oracle(seed):
+    """Seeded random shapes, boundaries per axis, Hamiltonians, parameters and schemes:
+    one step of the tile code against the oracle."""
+    import random_configs as RC
+    cfg = RC.random_config(seed)
+    h = RC.spacing(cfg)
+    bcs = cfg["bcs"] if len(cfg["shape"]) == 2 else (cfg["bcs"][0], cfg["bcs"][0])
+    prob = O.Problem(cfg["shape"], h, cfg["ham"], cfg["params"], bcs, scheme=cfg["scheme"],
+                     origin=RC.origin(cfg))
+    ref, info = O.rk3_step(prob, cfg["phi"], 0.0, 1.0, 0.5)
+    EM.set_scheme(cfg["scheme"])
+    EM.set_origin(*RC.origin(cfg))
+    try:
+        rc, got, ei = EM.rk3_step(cfg["phi"], h, cfg["ham"], cfg["params"], 0.0, 1.0, 0.5, bcs, 0)
+    finally:
+        EM.set_scheme(O.WENO_L)
+        EM.set_origin(0.0, 0.0)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), cfg
