@@ -43,3 +43,32 @@ def test_random_configuration_one_step(seed):
         assert gi.steps == 1
         err = float(np.abs(phi - ref).max() / scale)
         assert err <= tol, (seed, prec, err, cfg["shape"], cfg["ham"], cfg["bcs"])
+
+
+def test_random_configurations_through_the_server():
+    """The 2-D random configurations submitted together to the batched server (a few
+    steps each): each result is bitwise the single-grid result of the same solve."""
+    from paper_1909_13263_amd import workloads as W
+    cfgs = [c for c in (RC.random_config(s) for s in range(40)) if len(c["shape"]) == 2]
+    probs = []
+    for k, c in enumerate(cfgs):
+        probs.append((W.Problem(f"random{k}", c["shape"], c["lo"], c["hi"], c["bcs"], c["ham"],
+                                c["params"], 0.01), c))
+    srv = hjw.Server(hjw.FP32_MIXED, pool_bytes=128 << 20, max_active=16)
+    ids = {srv.submit(p, c["phi"], scheme=c["scheme"]): (p, c) for p, c in probs}
+    results = {r.rid: r for r in srv.drain()}
+    srv.close()
+    assert len(results) == len(probs)
+    for sid, (p, c) in ids.items():
+        g = hjw.Grid(c["shape"], c["lo"], c["hi"], c["bcs"], hjw.FP32_MIXED)
+        g.set_hamiltonian(c["ham"], c["params"])
+        if c["scheme"]:
+            g.set_scheme(c["scheme"])
+        g.set_phi(c["phi"])
+        info = g.step_to(p.t_final, p.cfl)
+        ref = g.get_phi()
+        g.close()
+        res = results[sid]
+        assert res.status == hjw.OK
+        assert res.info.steps == info.steps
+        assert np.array_equal(res.phi, ref), (p.name, c["shape"], c["ham"], c["bcs"])
