@@ -1,9 +1,9 @@
 /*
  * hjw.h - C ABI of the MI355X WENO-L Hamilton-Jacobi library.
  *
- * Solves phi_t + H(D phi) = 0, phi(x,0) = phi0(x), on a uniform 1-D or 2-D grid
- * (Rathan & Biswas, arXiv:1909.13263, eq. (HJ) restricted to Hamiltonians that
- * depend on D phi only) with the fifth-order arc-length WENO derivatives of
+ * Solves phi_t + H(x, D phi) = 0, phi(x,0) = phi0(x), on a uniform 1-D or 2-D grid
+ * (Rathan & Biswas, arXiv:1909.13263, eq. (HJ) restricted to built-in Hamiltonian
+ * families, see hjw_ham) with the fifth-order arc-length WENO derivatives of
  * Section 2 (Steps 1-4), the Lax-Friedrichs numerical Hamiltonian (eq. LF) and
  * third-order TVD Runge-Kutta in time (Step 5); two dimensions are handled
  * dimension by dimension (the Note closing Section 2).
@@ -13,8 +13,9 @@
  *     hjw_last_error() returns a thread-local message for the last failure.
  *   - Arrays are row-major with x fastest: phi[j*nx + i] = phi(x_i, y_j).  phi is
  *     exchanged as FP64 in every precision mode.
- *   - A periodic axis of n points covers [lo, hi) with x_i = lo + i*h, h = (hi-lo)/n;
- *     an extrapolated axis is cell-centred, x_i = lo + (i+1/2)*h.  n >= 8 per axis.
+ *   - A periodic or Dirichlet axis of n points covers [lo, hi) with x_i = lo + i*h,
+ *     h = (hi-lo)/n; an extrapolated axis is cell-centred, x_i = lo + (i+1/2)*h.
+ *     n >= 8 per axis (see hjw_bc).
  *   - The library owns hjw_grid objects.  The caller owns every pointer it passes:
  *     host arrays, device arrays and the device workspace given to hjw_bind, which
  *     must stay allocated until hjw_grid_destroy.

@@ -57,9 +57,28 @@ def build_emulator(out: str = EMU) -> str:
     return out
 
 
+C_EXAMPLE_SRC = os.path.join(ROOT, "tests", "c", "hjw_c_example.c")
+C_EXAMPLE = os.path.join(ROOT, "tests", "c", "hjw_c_example")
+
+
+def build_c_example(out: str = C_EXAMPLE) -> str:
+    """The C program that drives the C ABI without Python (test support): plain C99,
+    linked against libhjw.so (found next to the package through its run path) and the
+    HIP runtime."""
+    rocm = "/opt/rocm"
+    tmp = out + ".tmp"
+    _run(["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+          "-I", os.path.join(rocm, "include"), C_EXAMPLE_SRC, "-o", tmp,
+          "-L", PKG, "-lhjw", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+          "-Wl,-rpath,$ORIGIN/../../paper_1909_13263_amd", "-Wl,-rpath," + os.path.join(rocm, "lib")])
+    os.replace(tmp, out)
+    return out
+
+
 def build_all() -> None:
     build_library()
     build_emulator()
+    build_c_example()
 
 
 if __name__ == "__main__":
