@@ -134,10 +134,18 @@ struct Emu {
             std::fill(phiL.begin(), phiL.end(), P(NAN));
             std::fill(pnL.begin(), pnL.end(), P(NAN));
             std::fill(uL.begin(), uL.end(), T(NAN));
-            if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
+            const bool interior = TL::inside(a, x0, y0);
+            if (STAGE == kStageMid &&
+                (interior ||
+                 (sizeof(T) == 4 && a.bcx == kBcPeriodic && a.bcy == kBcPeriodic))) {
                 // the kernel's split second stage: gather, plan, then phi_1 in place
                 std::vector<typename TL::Gathered> gth(TL::kThreads);
-                for (int t = 0; t < TL::kThreads; ++t) TL::gather(t, a, x0, y0, gth[t]);
+                for (int t = 0; t < TL::kThreads; ++t) {
+                    if (interior)
+                        TL::template gather<false>(t, a, x0, y0, gth[t]);
+                    else
+                        TL::template gather<true>(t, a, x0, y0, gth[t]);
+                }
                 for (int t = 0; t < TL::kThreads; ++t)
                     TL::make_phi1(t, a, dt, ax, ay, phiL.data(), pnL.data(), gth[t]);
             } else {

@@ -255,13 +255,21 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     const int64_t y0 = int64_t(tile / a.nbx) * TY;
     const int tid = threadIdx.x;
     double dt, ax, ay;
-    if (STAGE == kStageMid && TL::inside(a, x0, y0)) {
+    const bool interior = TL::inside(a, x0, y0);
+    // periodic edge tiles take the same path on the FP32 stencil; on FP64 the second
+    // gather's code made the stage slower (the edge tiles load after the plan instead)
+    constexpr bool kEdgeEarly = sizeof(T) == 4;
+    if (STAGE == kStageMid &&
+        (interior || (kEdgeEarly && a.bcx == kBcPeriodic && a.bcy == kBcPeriodic))) {
         // the plan's loads, then the tile's, then the plan: the plan waits only for its
         // own loads (they were issued first) while the tile's are still in flight
         PlanIn pin;
         plan_issue(a, pin);
         typename TL::Gathered gth;
-        TL::gather(tid, a, x0, y0, gth);
+        if (!kEdgeEarly || interior)
+            TL::template gather<false>(tid, a, x0, y0, gth);
+        else
+            TL::template gather<kEdgeEarly>(tid, a, x0, y0, gth);
         dt = ax = ay = 0.0;
         if (!plan_finish(a, bid, pin, dt, ax, ay)) return;   // uniform over the workgroup
         TL::make_phi1(tid, a, dt, ax, ay, phiL, pnL, gth);

@@ -759,20 +759,34 @@ struct Tile {
     // Loads only, into registers (the idle threads of the last round load a valid
     // element): nothing here waits for them, so the step plan's loads, issued before,
     // and these overlap.
+    // EDGE: a tile at the edge of a grid periodic in both axes, whose halo indices wrap
+    // (each names one node, so the same one value per element as inside the grid).
+    template <bool EDGE>
     __host__ __device__ static void gather(int tid, const StageArgs<T, P>& a, int64_t x0,
                                            int64_t y0, Gathered& g) {
         const int64_t base = (y0 - 3) * a.nx + (x0 - 3);
+        const bool full = x0 + TX <= a.nx && y0 + TY <= a.ny;
 #pragma unroll
         for (int j = 0; j < kPerThread; ++j) {
             const int e = tid + j * kThreads;
             int r, c;
             plus_node(e < kPlusElems ? e : kPlusElems - 1, r, c);
-            const int64_t idx = base + r * a.nx + c;
+            int64_t idx;
+            if (!EDGE) {
+                idx = base + r * a.nx + c;
+            } else if (own_round(j) && full) {
+                idx = own_index(e, a, x0, y0);
+            } else {
+                int64_t i1;
+                int gg;
+                ghost_pair(a, x0 + c - 3, y0 + r - 3, idx, i1, gg);
+            }
             g.pn[j] = a.phi_n[idx];
             g.f[j] = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
         }
     }
-    // phi_1 of the plus-shaped region into phiL and phi^n of the tile into pnL.
+    // phi_1 of the plus-shaped region into phiL and phi^n of the tile into pnL (on a
+    // partial edge tile, the own nodes outside the grid get wrapped values no node uses).
     __host__ __device__ static void make_phi1(int tid, const StageArgs<T, P>& a, double dt,
                                               double ax, double ay, P* phiL, P* pnL,
                                               const Gathered& g) {
