@@ -184,7 +184,9 @@ hjw_status hjw_kernel_times(const hjw_grid *g, double *ms, int64_t *count);
 /* Average duration in milliseconds of each kernel of a step (ms[0] first stage,
  * ms[1] the plan launch, 0 where the second stage plans for itself, ms[2] second,
  * ms[3] third stage; ms holds 4 values, caller-owned), each launched reps times back
- * to back on the grid's stream between two HIP events, on the grid's current phi.
+ * to back on the grid's stream between two HIP events (after two untimed launches of
+ * the same kernel, so that the interval starts with the GPU busy), on the grid's
+ * current phi.
  * Takes one real step first; afterwards phi is undefined and must be set again
  * (hjw_set_phi) before stepping. */
 hjw_status hjw_time_kernels(hjw_grid *g, int reps, double *ms);

@@ -680,22 +680,24 @@ hjw_status hjw_time_kernels(hjw_grid* g, int reps, double* ms) {
     hipError_t err = hipSuccess;
     g->par ^= 1;   // launch against the records of the step just taken
     const bool plan = plan_launch(g);
+    auto launch = [&](int k) {
+        switch (g->prec) {
+        case HJW_FP64:
+            return launch_kind<double, double>(g, k);
+        case HJW_FP32_MIXED:
+            return launch_kind<float, double>(g, k);
+        default:
+            return launch_kind<float, float>(g, k);
+        }
+    };
     for (int k = 0; k < 4 && err == hipSuccess; ++k) {
         ms[k] = 0.0;
         if (k == 1 && !plan) continue;   // the plan runs inside the second stage
-        err = hipEventRecord(e0, g->stream);
-        for (int r = 0; r < reps && err == hipSuccess; ++r) {
-            switch (g->prec) {
-            case HJW_FP64:
-                err = launch_kind<double, double>(g, k);
-                break;
-            case HJW_FP32_MIXED:
-                err = launch_kind<float, double>(g, k);
-                break;
-            default:
-                err = launch_kind<float, float>(g, k);
-            }
-        }
+        // two untimed launches ahead of the start event keep the GPU busy while the
+        // host submits the timed ones: the interval holds no wait for the first launch
+        for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch(k);
+        if (err == hipSuccess) err = hipEventRecord(e0, g->stream);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch(k);
         if (err == hipSuccess) err = hipEventRecord(e1, g->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float t = 0.0f;

@@ -27,16 +27,43 @@
 namespace hjw {
 
 // ------------------------------------------------------------------ kernels
-template <typename T>
-__device__ inline T wave_min(T x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
-    return x;
+// Wave-wide min/max with DPP lane moves (no LDS round trip per step): two quad
+// permutations, then the half-row and row mirrors, leave every lane of each 16-lane row
+// with that row's fold; the four rows' values are read out with readlane.  The result
+// is uniform over the wave.  All 64 lanes must be active.
+template <int CTRL>
+__device__ inline int dpp_move(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline float dpp_move(float x) {
+    return __int_as_float(dpp_move<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ inline double dpp_move(double x) {
+    const int lo = dpp_move<CTRL>(__double2loint(x)), hi = dpp_move<CTRL>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float read_lane(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ inline double read_lane(double x, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                            __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+template <bool MAX, typename T>
+__device__ inline T wave_fold(T x) {
+    const auto f = [](T p, T q) { return MAX ? fmax(p, q) : fmin(p, q); };
+    x = f(x, dpp_move<0xB1>(x));    // quad_perm [1,0,3,2]
+    x = f(x, dpp_move<0x4E>(x));    // quad_perm [2,3,0,1]
+    x = f(x, dpp_move<0x141>(x));   // row_half_mirror: lane i <- lane 7-i of its half row
+    x = f(x, dpp_move<0x140>(x));   // row_mirror: lane i <- lane 15-i of its row
+    return f(f(read_lane(x, 0), read_lane(x, 16)), f(read_lane(x, 32), read_lane(x, 48)));
 }
 template <typename T>
-__device__ inline T wave_max(T x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
-    return x;
-}
+__device__ inline T wave_min(T x) { return wave_fold<false>(x); }
+template <typename T>
+__device__ inline T wave_max(T x) { return wave_fold<true>(x); }
 
 __device__ inline bool step_open(const DevState& s) {
     return s.bad == 0 && s.t < s.t_final && s.steps_left > 0;
@@ -72,26 +99,30 @@ template <int NW, typename T, typename P>
 __device__ inline void fold_range(const StageArgs<T, P>& a, int bid, T lu, T hu, T lv, T hv,
                                   bool bad) {
     __shared__ double red[NW][4];
+    __shared__ int red_bad[NW];
     const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     lu = wave_min(lu);
     hu = wave_max(hu);
     lv = wave_min(lv);
     hv = wave_max(hv);
-    const int anybad = __syncthreads_or(bad ? 1 : 0);
+    const bool wave_bad = __any(bad);
     if (lane == 0) {
         red[w][0] = double(lu);
         red[w][1] = double(hu);
         red[w][2] = double(lv);
         red[w][3] = double(hv);
+        red_bad[w] = wave_bad ? 1 : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double r0 = red[0][0], r1 = red[0][1], r2 = red[0][2], r3 = red[0][3];
+        int anybad = red_bad[0];
         for (int k = 1; k < NW; ++k) {
             r0 = fmin(r0, red[k][0]);
             r1 = fmax(r1, red[k][1]);
             r2 = fmin(r2, red[k][2]);
             r3 = fmax(r3, red[k][3]);
+            anybad |= red_bad[k];
         }
         RangeSlots* sl = static_cast<RangeSlots*>(a.slots);
         const int k = bid % kSlots;
@@ -296,7 +327,8 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     if (STAGE == kStagePre) {
         fold_range<TL::kThreads / 64>(a, bid, fin.lo_u, fin.hi_u, fin.lo_v, fin.hi_v, fin.bad);
     } else if (STAGE == kStageLast) {
-        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
+        // any wave that met a non-finite value raises the flag (the same store from each)
+        if (__any(fin.bad) && tid % 64 == 0) a.st[a.par ^ 1].bad = 1;
     }
 }
 
@@ -333,7 +365,8 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     if (STAGE == kStagePre) {
         fold_range<4>(a, int(blockIdx.x), fin.lo_u, fin.hi_u, T(0), T(0), fin.bad);
     } else if (STAGE == kStageLast) {
-        if (__syncthreads_or(fin.bad ? 1 : 0) && tid == 0) a.st[a.par ^ 1].bad = 1;
+        // any wave that met a non-finite value raises the flag (the same store from each)
+        if (__any(fin.bad) && tid % 64 == 0) a.st[a.par ^ 1].bad = 1;
     }
 }
 
