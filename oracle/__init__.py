@@ -17,7 +17,9 @@ Parity status of each routine (what pins it lives in ``tests/test_oracle_*``):
   dissipation                  closed forms pinned by brute-force box sampling;
                                the global-box reading itself is parity unpinned
   rk3_step / step_to           pinned: exact solutions (Examples 3.1-3.4), RK3 order;
-                               the dt rule is a reading (parity unpinned)
+                               the dt rule is a reading (parity unpinned); the stage
+                               times of H(x, t, phi, Dphi) pinned by TVD-RK3's stability
+                               polynomial and the closed form of H_TIMED
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ _SRC = os.path.join(_HERE, "weno_l_oracle.c")
 _LIB = os.path.join(_HERE, "libhjw_oracle.so")
 
 BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE = 0, 1, 2, 3, 4, 5, 6
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE, H_TIMED = range(8)
 WENO_L, WENO_JP = 0, 1
 
 
@@ -88,6 +90,8 @@ def _load():
         lib.orc_derivatives.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, dp, dp]
         lib.orc_hamiltonian_at.restype = ctypes.c_double
         lib.orc_hamiltonian_at.argtypes = [ctypes.POINTER(_Problem)] + [ctypes.c_double] * 4
+        lib.orc_hamiltonian_full.restype = ctypes.c_double
+        lib.orc_hamiltonian_full.argtypes = [ctypes.POINTER(_Problem)] + [ctypes.c_double] * 6
         lib.orc_hamiltonian.restype = ctypes.c_double
         lib.orc_hamiltonian.argtypes = [ctypes.POINTER(_Problem), ctypes.c_double, ctypes.c_double]
         lib.orc_dissipation.restype = None
@@ -238,10 +242,11 @@ def derivatives(prob: Problem, phi):
     return tuple(outs[:2]) if prob.dim == 1 else tuple(outs)
 
 
-def hamiltonian(prob: Problem, u, v=0.0, x=0.0, y=0.0):
-    """H(u, v) at the node (x, y) (only H_CONTROL depends on the position)."""
-    return _load().orc_hamiltonian_at(ctypes.byref(prob._c), float(x), float(y), float(u),
-                                      float(v))
+def hamiltonian(prob: Problem, u, v=0.0, x=0.0, y=0.0, t=0.0, phi=0.0):
+    """H(x, t, phi, u, v): only H_CONTROL depends on the position (x, y), only H_TIMED on
+    the time t and the node value phi."""
+    return _load().orc_hamiltonian_full(ctypes.byref(prob._c), float(x), float(y), float(t),
+                                        float(phi), float(u), float(v))
 
 
 def dissipation(prob: Problem, A, B, C=0.0, D=0.0):

@@ -43,6 +43,13 @@
  *     of the derivative ranges; every other node's stencil lies inside the grid.
  *     Example 3.10 names a Dirichlet boundary without giving the data: this is the
  *     reading.  PARITY UNPINNED by the paper (a reading).
+ *   - The general form phi_t + H(x, t, phi, D phi) = 0 (eq. (1.1)) enters Step 5
+ *     through L(phi_i) = -H_hat(x_i, t, phi_i, ...): the three stages of TVD-RK3
+ *     evaluate L at t_n, t_n + dt and t_n + dt/2 (the times their values
+ *     approximate), with phi_i the stage's own value at the node.  A zero-order term
+ *     lam phi adds |lam| to the rate of the time step.  No example of the paper
+ *     depends on t or phi; the TIMED family exercises both and is pinned by its closed
+ *     form and by TVD-RK3's stability polynomial.
  */
 #include <math.h>
 #include <stdint.h>
@@ -53,7 +60,7 @@
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_EXTRAP = 1, ORC_BC_DIRICHLET = 2 };
 enum { ORC_H_LINEAR = 0, ORC_H_BURGERS = 1, ORC_H_NEGCOS = 2, ORC_H_NORM = 3,
-       ORC_H_QUARTIC = 4, ORC_H_CONTROL = 5, ORC_H_CURVATURE = 6 };
+       ORC_H_QUARTIC = 4, ORC_H_CONTROL = 5, ORC_H_CURVATURE = 6, ORC_H_TIMED = 7 };
 enum { ORC_SCHEME_WENO_L = 0, ORC_SCHEME_WENO_JP = 1 };
 
 typedef struct {
@@ -328,6 +335,8 @@ int orc_derivatives(const orc_problem *p, const double *phi, double *um, double 
  *   CONTROL  sin(y) u + (sin(x) + sign v) v - sin(y)^2 / 2 - (1 - cos x)   (Example 3.11)
  *   CURVATURE s sqrt(u^2 + v^2 + k), with the curvature term of Example 3.13 (weight
  *            eps = hp[2]) added to the operator; see curvature_term()
+ *   TIMED    cos(w t) (a u + b v) + lam phi   (the general form of eq. (1.1); hp = {a, b,
+ *            w, lam}); see hamiltonian_full()
  * hp = {a, b, c} or {s, k} or {s, k, eps} (CONTROL has none).  In 1-D v is 0.  (x, y) is
  * the node.
  * ------------------------------------------------------------------------- */
@@ -364,6 +373,18 @@ double orc_hamiltonian_at(const orc_problem *p, double x, double y, double u, do
     default:
         return NAN;
     }
+}
+
+/* H(x, t, phi, u, v): the TIMED family depends on the time and on the node's value;
+ * every other family is H(x, u, v).  With phi0 given on periodic axes, TIMED has the
+ * solution phi(x, y, t) = exp(-lam t) phi0(x - a S(t), y - b S(t)), S(t) = sin(w t) / w
+ * (S(t) = t for w = 0). */
+double orc_hamiltonian_full(const orc_problem *p, double x, double y, double t, double phi,
+                            double u, double v)
+{
+    if (p->ham == ORC_H_TIMED)
+        return cos(p->hp[2] * t) * (p->hp[0] * u + p->hp[1] * v) + p->hp[3] * phi;
+    return orc_hamiltonian_at(p, x, y, u, v);
 }
 
 /* H at the origin (the Hamiltonians that do not depend on position). */
@@ -410,6 +431,7 @@ void orc_dissipation(const orc_problem *p, double A, double B, double C, double 
     }
     switch (p->ham) {
     case ORC_H_LINEAR:
+    case ORC_H_TIMED: /* |H_1| = |a cos(w t)| <= |a| at every stage time */
         *ax = fabs(h[0]);
         *ay = fabs(h[1]);
         return;
@@ -513,10 +535,10 @@ double orc_curvature_term(const orc_problem *p, const double *phi, int64_t i, in
     return N / (1.0 + px * px + py * py);
 }
 
-/* L(phi) = -H_hat at every node, given alpha (0 at held nodes), plus eps times the
- * curvature term for Example 3.13. */
-static int operator_L(const orc_problem *p, const double *phi, double ax, double ay, double *L,
-                      double *um, double *up, double *vm, double *vp)
+/* L(phi) = -H_hat at every node at the stage time t, given alpha (0 at held nodes),
+ * plus eps times the curvature term for Example 3.13. */
+static int operator_L(const orc_problem *p, const double *phi, double t, double ax, double ay,
+                      double *L, double *um, double *up, double *vm, double *vp)
 {
     if (orc_derivatives(p, phi, um, up, vm, vp) != 0)
         return -1;
@@ -525,7 +547,9 @@ static int operator_L(const orc_problem *p, const double *phi, double ax, double
         const double a = (p->dim == 2) ? vm[k] : 0.0, b = (p->dim == 2) ? vp[k] : 0.0;
         const double x = p->x0 + (double)(k % p->nx) * p->dx;
         const double y = (p->dim == 2) ? p->y0 + (double)(k / p->nx) * p->dy : 0.0;
-        L[k] = held(p, k) ? 0.0 : -orc_lax_friedrichs_at(p, x, y, um[k], up[k], a, b, ax, ay);
+        const double H = orc_hamiltonian_full(p, x, y, t, phi[k], 0.5 * (up[k] + um[k]),
+                                              0.5 * (a + b));
+        L[k] = held(p, k) ? 0.0 : -(H - ax * 0.5 * (up[k] - um[k]) - ay * 0.5 * (b - a));
         if (p->ham == ORC_H_CURVATURE && !held(p, k))
             L[k] += p->hp[2] * orc_curvature_term(p, phi, k % p->nx, k / p->nx);
     }
@@ -585,6 +609,9 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
      * enters the rate (a reading; the paper gives no time step for Example 3.13) */
     if (p->ham == ORC_H_CURVATURE)
         rate += 2.0 * p->hp[2] * (1.0 / (p->dx * p->dx) + 1.0 / (p->dy * p->dy));
+    /* the zero-order term lam phi: |lam| dt <= cfl (a reading, see the header) */
+    if (p->ham == ORC_H_TIMED)
+        rate += fabs(p->hp[3]);
     const double remaining = t_final - t;
     double dt = (rate > 0.0) ? cfl / rate : remaining;
     int last = 0;
@@ -597,16 +624,16 @@ int orc_rk3_step(const orc_problem *p, double *phi, double t, double t_final, do
         goto out;
     }
 
-    /* phi_1 = phi_0 + dt L(phi_0) */
-    if (operator_L(p, p0, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
+    /* phi_1 = phi_0 + dt L(phi_0), L at t_n */
+    if (operator_L(p, p0, t, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
     for (int64_t k = 0; k < n; ++k)
         p1[k] = held(p, k) ? p0[k] : p0[k] + dt * L[k];
-    /* phi_2 = 3/4 phi_0 + 1/4 (phi_1 + dt L(phi_1)) */
-    if (operator_L(p, p1, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
+    /* phi_2 = 3/4 phi_0 + 1/4 (phi_1 + dt L(phi_1)), L at t_n + dt */
+    if (operator_L(p, p1, t + dt, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
     for (int64_t k = 0; k < n; ++k)
         p2[k] = held(p, k) ? p0[k] : 0.75 * p0[k] + 0.25 * (p1[k] + dt * L[k]);
-    /* phi^{n+1} = 1/3 phi_0 + 2/3 (phi_2 + dt L(phi_2)) */
-    if (operator_L(p, p2, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
+    /* phi^{n+1} = 1/3 phi_0 + 2/3 (phi_2 + dt L(phi_2)), L at t_n + dt/2 */
+    if (operator_L(p, p2, t + 0.5 * dt, ax, ay, L, um, up, vm, vp)) { rc = -1; goto out; }
     for (int64_t k = 0; k < n; ++k) {
         phi[k] = held(p, k) ? p0[k] : (1.0 / 3.0) * p0[k] + (2.0 / 3.0) * (p2[k] + dt * L[k]);
         if (!isfinite(phi[k]))

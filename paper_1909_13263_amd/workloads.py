@@ -20,6 +20,10 @@ Figure-only examples of Section 3 (no printed numbers; see ``figure_examples``):
   ex311_control  Example 3.11, the optimal-control equation on [-pi,pi)^2, phi0 = 0, t = 1
   ex312_eikonal  Example 3.12, phi_t + sqrt(phi_x^2+phi_y^2+1) = 0 on [0,1)^2, t = 0.6
 
+The general form phi_t + H(x, t, phi, D phi) = 0 of eq. (1.1) (no example of the paper):
+  timed1d, timed2d  H = cos(w t)(a phi_x + b phi_y) + lam phi on [-1,1) / [-1,1)^2,
+                    phi0 = -cos(pi x) (+ sin(pi y)/2 in 2-D)
+
 Grid conventions: a periodic axis of n points on [lo, hi) has x_i = lo + i h,
 h = (hi-lo)/n; an extrapolated axis is cell-centred, x_i = lo + (i+1/2) h.
 Arrays are row-major with x fastest: phi[j, i] = phi(x_i, y_j).
@@ -33,7 +37,7 @@ from dataclasses import dataclass
 import numpy as np
 
 BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE = 0, 1, 2, 3, 4, 5, 6
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE, H_TIMED = range(8)
 CIRCLE_SEED = 13263
 SERVE_SEED = 1909
 
@@ -137,6 +141,19 @@ def ex313_curvature(n=60, eps=0.1, t_final=0.6):
                    H_CURVATURE, (-1.0, 1.0, float(eps)), t_final)
 
 
+def timed1d(n=160, a=1.0, w=2.0 * math.pi, lam=0.5, t_final=1.0):
+    """phi_t + cos(w t) a phi_x + lam phi = 0, phi0 = -cos(pi x) on [-1,1)."""
+    return Problem("timed1d", (n,), (-1.0,), (1.0,), BC_PERIODIC, H_TIMED,
+                   (float(a), 0.0, float(w), float(lam)), t_final)
+
+
+def timed2d(n=128, a=1.0, b=-0.5, w=2.0 * math.pi, lam=0.5, t_final=1.0, ny=None):
+    """phi_t + cos(w t)(a phi_x + b phi_y) + lam phi = 0, phi0 = -cos(pi x) + sin(pi y)/2
+    on [-1,1)^2."""
+    return Problem("timed2d", (ny or n, n), (-1.0, -1.0), (1.0, 1.0), BC_PERIODIC, H_TIMED,
+                   (float(a), float(b), float(w), float(lam)), t_final)
+
+
 def figure_examples():
     """The figure-only examples of Section 3 at the paper's grid sizes and times (with
     the 1-D Burgers and -cos runs past the kink time, Examples 3.6 and 3.7, and the 2-D
@@ -192,6 +209,11 @@ def initial_data(p: Problem) -> np.ndarray:
     if p.name == "ex313_curvature":
         x, y = p.coords(0), p.coords(1)
         return 1 - 0.25 * (np.cos(2 * math.pi * x)[None, :] - 1) * (np.cos(2 * math.pi * y)[:, None] - 1)
+    if p.name == "timed1d":
+        return -np.cos(math.pi * p.coords(0))
+    if p.name == "timed2d":
+        x, y = p.coords(0), p.coords(1)
+        return -np.cos(math.pi * x)[None, :] + 0.5 * np.sin(math.pi * y)[:, None]
     if p.name in ("burgers2d", "negcos2d"):
         x = p.coords(0)
         y = p.coords(1)

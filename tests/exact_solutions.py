@@ -6,6 +6,10 @@ phi_t + H(phi_x) = 0 with smooth phi0 is solved before characteristics cross by
 The 2-D problems of Examples 3.3 and 3.4 depend on zeta = (x+y)/2 only: with
 phi(x,y) = chi((x+y)/2), phi_x + phi_y = chi', so chi solves the 1-D equation with
 chi0 = -cos(pi zeta).
+
+The general form phi_t + H(x, t, phi, D phi) = 0 with H = cos(w t)(a phi_x + b phi_y) + lam phi
+(a linear transport with a time-dependent speed and a decay) has the solution
+phi(x, y, t) = exp(-lam t) phi0(x - a S(t), y - b S(t)), S(t) = sin(w t) / w (S = t for w = 0).
 """
 from __future__ import annotations
 
@@ -85,3 +89,17 @@ def errors(num, exact, cell_volume):
     """(L_inf, L_1) with L_1 = cell volume * sum |e| (the domain integral)."""
     e = np.abs(np.asarray(num) - np.asarray(exact))
     return float(e.max()), float(cell_volume * e.sum())
+
+
+def timed(pr, t):
+    """The solution of the timed1d / timed2d problems (periodic axes) at time t."""
+    a, b, w, lam = pr.params
+    s = math.sin(w * t) / w if w != 0.0 else t
+    lo, hi = pr.lo[0], pr.hi[0]
+    x = lo + np.mod(pr.coords(0) - a * s - lo, hi - lo)
+    if pr.dim == 1:
+        return math.exp(-lam * t) * -np.cos(math.pi * x)
+    lo, hi = pr.lo[1], pr.hi[1]
+    y = lo + np.mod(pr.coords(1) - b * s - lo, hi - lo)
+    return math.exp(-lam * t) * (-np.cos(math.pi * x)[None, :] +
+                                 0.5 * np.sin(math.pi * y)[:, None])
