@@ -1,8 +1,8 @@
 /*
  * hjw.h - C ABI of the MI355X WENO-L Hamilton-Jacobi library.
  *
- * Solves phi_t + H(x, D phi) = 0, phi(x,0) = phi0(x), on a uniform 1-D or 2-D grid
- * (Rathan & Biswas, arXiv:1909.13263, eq. (HJ) restricted to built-in Hamiltonian
+ * Solves phi_t + H(x, t, phi, D phi) = 0, phi(x,0) = phi0(x), on a uniform 1-D or 2-D
+ * grid (Rathan & Biswas, arXiv:1909.13263, eq. (1.1) restricted to built-in Hamiltonian
  * families, see hjw_ham) with the fifth-order arc-length WENO derivatives of
  * Section 2 (Steps 1-4), the Lax-Friedrichs numerical Hamiltonian (eq. LF) and
  * third-order TVD Runge-Kutta in time (Step 5); two dimensions are handled
@@ -86,6 +86,12 @@ typedef enum { HJW_WENO_L = 0, HJW_WENO_JP = 1 } hjw_scheme;
  *            the time-step rate gains 2 eps (1/dx^2 + 1/dy^2).  Example 3.13 is
  *            p = {-1, 1, eps}.  2-D grids with periodic or Dirichlet axes only (EINVAL
  *            otherwise).
+ *   TIMED    cos(p[2]*t) (p[0]*u + p[1]*v) + p[3]*phi: the general form of eq. (1.1),
+ *            depending on the time and on the node's value (no example of the paper).
+ *            The three RK stages evaluate it at t_n, t_n + dt and t_n + dt/2 with each
+ *            stage's own phi; the dissipation is |p[0]|, |p[1]|, and the time-step rate
+ *            gains |p[3]|.  Its grids run kernels of their own with 64 x 16 tiles
+ *            (EINVAL with HJW_OPT_TILE_ROWS = 32).
  * The dissipation of eq. (LF) is the maximum of |H_u|, |H_v| over the box of the
  * step's derivative ranges (CONTROL: the bounds 1 and 2 of its coefficients). */
 typedef enum {
@@ -95,7 +101,8 @@ typedef enum {
     HJW_H_NORM = 3,
     HJW_H_QUARTIC = 4,
     HJW_H_CONTROL = 5,
-    HJW_H_CURVATURE = 6
+    HJW_H_CURVATURE = 6,
+    HJW_H_TIMED = 7
 } hjw_ham;
 
 /* Options for hjw_set_option. */
@@ -106,7 +113,8 @@ typedef enum {
                                   HIP events on the grid's stream; resets the totals that
                                   hjw_kernel_times reports.  0 (default): off. */
     HJW_OPT_TILE_ROWS = 2,     /* 2-D tile height: 16 (default: 64 x 16 nodes) or 32 (64 x 32
-                                  nodes, 8-node segments only).  Results are identical. */
+                                  nodes, 8-node segments only; not with HJW_H_TIMED, whose
+                                  kernels take 16-row tiles).  Results are identical. */
     HJW_OPT_SEGMENT = 3,       /* nodes each thread marches in the 2-D sweeps: 0 (default)
                                   automatic, 4 (FP32 stencil, 16-row tiles: 512 threads per
                                   tile) or 8 (256 threads per 16-row tile).  Results are
@@ -184,9 +192,10 @@ hjw_status hjw_kernel_times(const hjw_grid *g, double *ms, int64_t *count);
 /* Average duration in milliseconds of each kernel of a step (ms[0] first stage,
  * ms[1] the plan launch, 0 where the second stage plans for itself, ms[2] second,
  * ms[3] third stage; ms holds 4 values, caller-owned), each launched reps times back
- * to back on the grid's stream between two HIP events (after two untimed launches of
- * the same kernel, so that the interval starts with the GPU busy), on the grid's
- * current phi.
+ * to back on the grid's stream between two HIP events, on the grid's current phi.
+ * Ahead of them the GPU waits about 2 ms in a hold kernel while the host submits every
+ * launch, then runs two untimed launches of the same kernel: the timed ones start back
+ * to back however slowly the host submits.
  * Takes one real step first; afterwards phi is undefined and must be set again
  * (hjw_set_phi) before stepping. */
 hjw_status hjw_time_kernels(hjw_grid *g, int reps, double *ms);

@@ -190,17 +190,25 @@ template <typename T, typename P, int STAGE>
 hipError_t launch_stage(const hjw_grid* g, StageArgs<T, P> a) {
     const dim3 grid(unsigned(g->nbx * g->nby));
     constexpr bool kNarrow = !std::is_same<T, double>::value;   // the S = 4 kernels
-    if (g->dim == 2 && g->tile_rows == 32)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32, 8>), grid, dim3(threads2d(32, 8)), 0,
-                           g->stream, a);
+    // the time- and phi-dependent family has kernels of its own (16-row tiles, 8-node
+    // segments), so that the other families' kernels carry none of its code
+    constexpr bool kH = STAGE != kStageDeriv;   // the derivatives do not evaluate H
+    if (kH && g->ham == HJW_H_TIMED && g->dim == 2)
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, 8, true>), grid, dim3(threads2d(16, 8)),
+                           0, g->stream, a);
+    else if (kH && g->ham == HJW_H_TIMED)
+        hipLaunchKernelGGL((k_stage1d<T, P, STAGE, true>), grid, dim3(256), 0, g->stream, a);
+    else if (g->dim == 2 && g->tile_rows == 32)
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32, 8, false>), grid, dim3(threads2d(32, 8)),
+                           0, g->stream, a);
     else if (g->dim == 2 && kNarrow && segment(g) == 4)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, kNarrow ? 4 : 8>), grid,
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, kNarrow ? 4 : 8, false>), grid,
                            dim3(threads2d(16, 4)), 0, g->stream, a);
     else if (g->dim == 2)
-        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, 8>), grid, dim3(threads2d(16, 8)), 0,
-                           g->stream, a);
+        hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, 8, false>), grid, dim3(threads2d(16, 8)),
+                           0, g->stream, a);
     else
-        hipLaunchKernelGGL((k_stage1d<T, P, STAGE>), grid, dim3(256), 0, g->stream, a);
+        hipLaunchKernelGGL((k_stage1d<T, P, STAGE, false>), grid, dim3(256), 0, g->stream, a);
     return hipGetLastError();
 }
 
@@ -469,7 +477,7 @@ hjw_status hjw_set_scheme(hjw_grid* g, int scheme) {
 
 hjw_status hjw_set_hamiltonian(hjw_grid* g, int kind, const double* params, int nparams) {
     if (!g) return fail(HJW_EINVAL, "grid is NULL");
-    if (kind < HJW_H_LINEAR || kind > HJW_H_CURVATURE)
+    if (kind < HJW_H_LINEAR || kind > HJW_H_TIMED)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", kind);
     if (nparams < 0 || nparams > 4 || (nparams > 0 && !params))
         return fail(HJW_EINVAL, "bad parameter list");
@@ -480,6 +488,8 @@ hjw_status hjw_set_hamiltonian(hjw_grid* g, int kind, const double* params, int 
     }
     if ((kind == HJW_H_NORM || kind == HJW_H_CURVATURE) && p[1] < 0.0)
         return fail(HJW_EINVAL, "NORM needs p[1] >= 0");
+    if (kind == HJW_H_TIMED && g->dim == 2 && g->tile_rows == 32)
+        return fail(HJW_EINVAL, "the TIMED family runs 16-row tiles");
     if (kind == HJW_H_CURVATURE) {
         if (g->dim != 2 || g->bcx == HJW_BC_EXTRAP || g->bcy == HJW_BC_EXTRAP)
             return fail(HJW_EINVAL, "CURVATURE needs a 2-D grid with periodic or Dirichlet axes");
@@ -638,6 +648,8 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
         if (value != 16 && value != 32) return fail(HJW_EINVAL, "tile rows must be 16 or 32");
         if (value == 32 && g->seg_opt == 4)
             return fail(HJW_EINVAL, "32-row tiles take 8-node segments");
+        if (value == 32 && g->ham_set && g->ham == HJW_H_TIMED)
+            return fail(HJW_EINVAL, "the TIMED family runs 16-row tiles");
         g->tile_rows = int(value);
         if (g->dim == 2) g->nby = int((g->ny + g->tile_rows - 1) / g->tile_rows);
         drop_graph(g);
@@ -690,11 +702,20 @@ hjw_status hjw_time_kernels(hjw_grid* g, int reps, double* ms) {
             return launch_kind<float, float>(g, k);
         }
     };
+    // about 2 ms of the wall clock: longer than the host takes to submit the launches
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;
+    const int64_t hold_ticks = int64_t(khz) * 2;
     for (int k = 0; k < 4 && err == hipSuccess; ++k) {
         ms[k] = 0.0;
         if (k == 1 && !plan) continue;   // the plan runs inside the second stage
-        // two untimed launches ahead of the start event keep the GPU busy while the
-        // host submits the timed ones: the interval holds no wait for the first launch
+        // the GPU waits in a hold kernel while the host submits every launch, so the timed
+        // ones start back to back however slowly the host submits (under a profiler, say);
+        // two untimed launches after the hold bring the clocks and caches up
+        hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, g->stream, hold_ticks);
+        err = hipGetLastError();
         for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch(k);
         if (err == hipSuccess) err = hipEventRecord(e0, g->stream);
         for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch(k);

@@ -58,7 +58,7 @@ struct Emu {
     Guarded<T> flux;
     Guarded<double> partials;
     Guarded<double> d0, d1, d2, d3;
-    DevState st{};
+    DevState st[2]{};   // the step's record and the planned one, as on the GPU
     int nbx, nby;
     bool overrun = false;
 
@@ -82,7 +82,7 @@ struct Emu {
         a.dout1 = d1.data();
         a.dout2 = d2.data();
         a.dout3 = d3.data();
-        a.st = &st;
+        a.st = st;
         a.par = 0;
         a.slots = nullptr;
         a.nx = pr.nx;
@@ -101,7 +101,10 @@ struct Emu {
         a.dxD = pr.dx;
         a.dyD = pr.dy;
         a.ham = pr.ham;
-        for (int k = 0; k < 4; ++k) a.hpT[k] = T(pr.hp[k]);
+        for (int k = 0; k < 4; ++k) {
+            a.hpT[k] = T(pr.hp[k]);
+            a.hpD[k] = pr.hp[k];
+        }
         a.nbx = nbx;
         a.nby = nby;
         a.remap = 0;
@@ -168,7 +171,7 @@ struct Emu {
                 // row threads (t < kHalf) finish from the stash, column threads from registers
                 const bool col_half = t >= TL::kHalf;
                 const int u = col_half ? t - TL::kHalf : t;
-                Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
+                Finisher<STAGE, T, P, true> fin(a, x0, y0, dt, ax, ay, 2);
                 TL::finish(u, col_half, uL.data(), &vm[size_t(u) * S], &vp[size_t(u) * S],
                            vL.data(), phiL.data(), kCenter ? pnL.data() : nullptr, fin);
                 lu = std::fmin(lu, double(fin.lo_u));
@@ -195,7 +198,7 @@ struct Emu {
             for (int t = 0; t < TL::kThreads; ++t)
                 TL::template load<STAGE>(t, a, x0, dt, ax, 0.0, phiL.data(), pnL.data());
             for (int t = 0; t < TL::kThreads; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
-            Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
+            Finisher<STAGE, T, P, true> fin(a, x0, 0, dt, ax, 0.0, 1);
             for (int c = 0; c < kTX1; ++c)
                 fin(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], pnL[c]);
             write_partial(b, double(fin.lo_u), double(fin.hi_u), 0.0, 0.0, fin.bad);
@@ -255,10 +258,11 @@ template <typename T, typename P>
 int step(const Problem& pr, double* phi, double t, double t_final, double cfl, double* info) {
     Emu<T, P> e(pr);
     for (size_t k = 0; k < e.n; ++k) e.phi.data()[k] = P(phi[k]);
-    e.st.t = t;
-    e.st.t_final = t_final;
-    e.st.cfl = cfl;
-    e.st.steps_left = 1;
+    e.st[0].t = t;
+    e.st[0].t_final = t_final;
+    e.st[0].cfl = cfl;
+    e.st[0].steps_left = 1;
+    e.st[1] = e.st[0];
     StageArgs<T, P> a = e.args();
     e.template stage<kStagePre>(a, 0.0, 0.0, 0.0);
     // the finalize kernel, serially
@@ -273,21 +277,22 @@ int step(const Problem& pr, double* phi, double t, double t_final, double cfl, d
         r[3] = std::fmax(r[3], p[3]);
         bad = bad || p[4] != 0.0;
     }
-    if (!bad) plan_step(e.st, pr.ham, pr.hp, pr.dim, 1.0 / pr.dx, 1.0 / pr.dy, r);
-    if (bad || e.st.bad) {
+    DevState& ns = e.st[1];   // st[0] keeps t_n for the stages
+    if (!bad) plan_step(ns, pr.ham, pr.hp, pr.dim, 1.0 / pr.dx, 1.0 / pr.dy, r);
+    if (bad || ns.bad) {
         info[8] = 1.0;
         return -5;
     }
     a.out = e.phi2.data();
-    e.template stage<kStageMid>(a, e.st.dt, e.st.alpha_x, e.st.alpha_y);
+    e.template stage<kStageMid>(a, ns.dt, ns.alpha_x, ns.alpha_y);
     a.out = e.phi.data();
-    e.template stage<kStageLast>(a, e.st.dt, e.st.alpha_x, e.st.alpha_y);
+    e.template stage<kStageLast>(a, ns.dt, ns.alpha_x, ns.alpha_y);
     for (size_t k = 0; k < e.n; ++k) phi[k] = double(e.phi.data()[k]);
-    info[0] = e.st.t;
-    info[1] = e.st.dt;
-    info[2] = e.st.alpha_x;
-    info[3] = e.st.alpha_y;
-    for (int k = 0; k < 4; ++k) info[4 + k] = e.st.range[k];
+    info[0] = ns.t;
+    info[1] = ns.dt;
+    info[2] = ns.alpha_x;
+    info[3] = ns.alpha_y;
+    for (int k = 0; k < 4; ++k) info[4 + k] = ns.range[k];
     info[8] = 0.0;
     return e.guards() ? 0 : -7;
 }

@@ -271,7 +271,7 @@ __device__ inline bool stage_entry(const StageArgs<T, P>& a, int bid, double& dt
 // One workgroup's share of a stage on a 2-D grid: bid is the workgroup's index among
 // the grid's nbx * nby tiles; threads2d(TY, S) threads, half row and half column
 // threads, each marching S nodes.
-template <typename T, typename P, int STAGE, int TY, int S>
+template <typename T, typename P, int STAGE, int TY, int S, bool TIMED>
 __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     using TL = Tile<T, P, kTX, TY, S, S>;
     static_assert(TL::kThreads == threads2d(TY, S), "launch bounds");
@@ -320,7 +320,7 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
         TL::stash(tid - TL::kHalf, vm, vp, vL);
     }
     __syncthreads();
-    Finisher<STAGE, T, P> fin(a, x0, y0, dt, ax, ay, 2);
+    Finisher<STAGE, T, P, TIMED> fin(a, x0, y0, dt, ax, ay, 2);
     TL::finish(rows ? tid : tid - TL::kHalf, !rows, uL, vm, vp, vL, phiL,
                kCenter ? pnL : nullptr, fin);
 
@@ -332,12 +332,14 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     }
 }
 
-template <typename T, typename P, int STAGE, int TY, int S>
+// TIMED: the grid's Hamiltonian may be the time- and phi-dependent family; the kernels of
+// every other family are compiled without its code.
+template <typename T, typename P, int STAGE, int TY, int S, bool TIMED>
 __global__ __launch_bounds__(threads2d(TY, S)) void k_stage2d(StageArgs<T, P> a) {
-    stage_tile2d<T, P, STAGE, TY, S>(a, int(blockIdx.x));
+    stage_tile2d<T, P, STAGE, TY, S, TIMED>(a, int(blockIdx.x));
 }
 
-template <typename T, typename P, int STAGE>
+template <typename T, typename P, int STAGE, bool TIMED>
 __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     using TL = Tile1D<T, P, kTX1, kS1>;
     constexpr bool kCenter = STAGE == kStageMid || STAGE == kStageLast;
@@ -352,15 +354,20 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     __syncthreads();
     TL::sweep_x(tid, a, phiL, uL);
     __syncthreads();
-    Finisher<STAGE, T, P> fin(a, x0, 0, dt, ax, 0.0, 1);
-    if (fin.extended()) {
+    Finisher<STAGE, T, P, TIMED> fin(a, x0, 0, dt, ax, 0.0, 1);
+    const int mode = fin.mode();
+    if (TIMED && mode == kNodeTimed) {
         for (int c = tid; c < kTX1; c += 256)
-            fin.template node<true>(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3],
-                                    kCenter ? pnL[c] : P(0));
+            fin.template node<TIMED ? kNodeTimed : kNodePlain>(
+                c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3], kCenter ? pnL[c] : P(0));
+    } else if (mode == kNodeExtended) {
+        for (int c = tid; c < kTX1; c += 256)
+            fin.template node<kNodeExtended>(c, 0, uL[c], uL[kTX1 + c], T(0), T(0),
+                                             phiL[c + 3], kCenter ? pnL[c] : P(0));
     } else {
         for (int c = tid; c < kTX1; c += 256)
-            fin.template node<false>(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3],
-                                     kCenter ? pnL[c] : P(0));
+            fin.template node<kNodePlain>(c, 0, uL[c], uL[kTX1 + c], T(0), T(0), phiL[c + 3],
+                                          kCenter ? pnL[c] : P(0));
     }
     if (STAGE == kStagePre) {
         fold_range<4>(a, int(blockIdx.x), fin.lo_u, fin.hi_u, T(0), T(0), fin.bad);
@@ -377,6 +384,16 @@ __global__ __launch_bounds__(64) void k_plan(StageArgs<T, P> a) {
     double dt, ax, ay;
     a.plan_ready = 0;   // the second stage's arguments say the plan is published: by this
     (void)plan_in_block(a, 0, dt, ax, ay);
+}
+
+// Keeps one wave busy for about `ticks` of the constant-rate wall clock (at most 2^22
+// short sleeps), so that the launches the host enqueues meanwhile then run back to back.
+static __global__ void k_hold(int64_t ticks) {
+    const long long t0 = wall_clock64();
+    for (int k = 0; k < (1 << 22); ++k) {
+        if (wall_clock64() - t0 >= ticks) break;
+        __builtin_amdgcn_s_sleep(8);
+    }
 }
 
 static __global__ void k_set_target(DevState* st, double t_final, double cfl, int64_t steps_left) {

@@ -58,7 +58,8 @@ __global__ __launch_bounds__(threads2d(16, S)) void k_stage2d_batch(const StageA
     // the second stage writes phi_2, the third phi^{n+1} over phi^n
     if (STAGE == kStageMid) a.out = const_cast<P*>(a.phi_s);
     if (STAGE == kStageLast) a.out = const_cast<P*>(a.phi_n);
-    stage_tile2d<T, P, STAGE, 16, S>(a, b - tile_start[lo]);
+    // one launch serves solves of every family, the time- and phi-dependent one included
+    stage_tile2d<T, P, STAGE, 16, S, true>(a, b - tile_start[lo]);
 }
 
 // The step plans of all admitted solves, one wave each (workgroup g plans solve g).
@@ -205,7 +206,7 @@ hjw_status validate(const hjw_request& r) {
             r.bc[d] != HJW_BC_DIRICHLET)
             return fail(HJW_EINVAL, "request axis %d: unknown boundary %d", d, r.bc[d]);
     }
-    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_CURVATURE)
+    if (r.ham < HJW_H_LINEAR || r.ham > HJW_H_TIMED)
         return fail(HJW_EINVAL, "unknown Hamiltonian %d", r.ham);
     if (r.scheme != HJW_WENO_L && r.scheme != HJW_WENO_JP)
         return fail(HJW_EINVAL, "unknown scheme %d", r.scheme);

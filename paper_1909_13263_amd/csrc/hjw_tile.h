@@ -54,6 +54,13 @@ constexpr int kHNorm = 3;
 constexpr int kHQuartic = 4;
 constexpr int kHControl = 5;
 constexpr int kHCurvature = 6;   // NORM plus the curvature term of Example 3.13
+constexpr int kHTimed = 7;       // cos(w t)(a u + b v) + lam phi: depends on t and phi
+
+// Node variants of the finish (Finisher::mode): plain; with held Dirichlet layers or the
+// curvature term; the time- and phi-dependent family (held layers possible).
+constexpr int kNodePlain = 0;
+constexpr int kNodeExtended = 1;
+constexpr int kNodeTimed = 2;
 
 // Stage kinds of one Runge-Kutta step.
 constexpr int kStagePre = 0;    // derivatives of phi^n -> Hbar, Dx, Dy, block ranges
@@ -350,7 +357,8 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
 
 // ---------------------------------------------------------------- Hamiltonians
 // H(u, v) at the node (x, y); only the control Hamiltonian of Example 3.11 depends on
-// the position:
+// the position (the family that depends on t and phi, TIMED, is evaluated by the
+// finisher, which holds the stage time):
 //   LINEAR a u + b v; BURGERS s^2/2; NEGCOS -cos s; QUARTIC (s^2-1)(s^2-4)/4 with
 //   s = a u + b v + c; NORM and CURVATURE k0 sqrt(u^2 + v^2 + k1) (the curvature term
 //   is added by the finisher);
@@ -411,7 +419,8 @@ __host__ __device__ inline void dissipation(int kind, const double* p, int dim, 
         C = 0.0;
         D = 0.0;
     }
-    if (kind == kHLinear) {
+    if (kind == kHLinear || kind == kHTimed) {
+        // TIMED: |H_u| = |a cos(w t)| <= |a| at every stage time
         ax = fabs(p[0]);
         ay = fabs(p[1]);
     } else if (kind == kHControl) {
@@ -452,6 +461,8 @@ __host__ __device__ inline void plan_step(DevState& s, int kind, const double* p
     double rate = mul_rn(ax, ihx) + (dim == 2 ? mul_rn(ay, ihy) : 0.0);
     // the curvature term diffuses with a coefficient of at most eps = p[2]
     if (kind == kHCurvature) rate += 2.0 * p[2] * (mul_rn(ihx, ihx) + mul_rn(ihy, ihy));
+    // the zero-order term lam phi of TIMED: |lam| dt <= cfl
+    if (kind == kHTimed) rate += fabs(p[3]);
     const double remaining = s.t_final - s.t;
     double dt = rate > 0.0 ? s.cfl / rate : remaining;
     double tn = s.t + dt;
@@ -862,12 +873,19 @@ struct Tile {
                                            const P* pnL, Fin& fin) {
         fin.tileL = phiL;
         fin.pw = PW;
-        if (fin.extended())
-            finish_nodes<true>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
+        const int mode = fin.mode();
+        if constexpr (Fin::kTimed) {
+            if (mode == kNodeTimed) {
+                finish_nodes<kNodeTimed>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
+                return;
+            }
+        }
+        if (mode == kNodeExtended)
+            finish_nodes<kNodeExtended>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
         else
-            finish_nodes<false>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
+            finish_nodes<kNodePlain>(t, col_half, uL, vm, vp, vL, phiL, pnL, fin);
     }
-    template <bool EXT, class Fin>
+    template <int MODE, class Fin>
     __host__ __device__ static void finish_nodes(int t, bool col_half, const T* uL, const T* vm,
                                                  const T* vp, const T* vL, const P* phiL,
                                                  const P* pnL, Fin& fin) {
@@ -879,7 +897,7 @@ struct Tile {
             const int slot = (seg * kKeep + j) * TX + col;
             const T m = col_half ? vm[j] : vL[slot];
             const T p = col_half ? vp[j] : vL[kVElems / 2 + slot];
-            fin.template node<EXT>(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col],
+            fin.template node<MODE>(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col],
                                    m, p, phiL[(row + 3) * PW + col + 3],
                                    pnL ? pnL[row * TX + col] : P(0));
         }
@@ -923,10 +941,14 @@ struct Tile1D {
 };
 
 // ---------------------------------------------------------------- node finish
+
 // Per-node work after both sweeps, for each stage kind.  Holds running
 // min/max of the derivatives for the pre-stage.
-template <int STAGE, typename T, typename P>
+// TIMED: the launch may carry the time- and phi-dependent family (its code is compiled
+// only into kernels that take it, so that it does not change the others' code).
+template <int STAGE, typename T, typename P, bool TIMED>
 struct Finisher {
+    static constexpr bool kTimed = TIMED;
     const StageArgs<T, P>& a;
     int64_t x0, y0;
     double dt, ax, ay;
@@ -935,11 +957,20 @@ struct Finisher {
     int dim;
     const P* tileL = nullptr;   // the stage input on the tile (2-D; curvature term only)
     int pw = 0;                 // its row pitch
+    T cos_wt = T(0);            // TIMED: cos(w t) at this stage's time
 
     __host__ __device__ Finisher(const StageArgs<T, P>& args, int64_t x0_, int64_t y0_,
                                  double dt_, double ax_, double ay_, int dim_)
         : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), lo_u(T(INFINITY)),
-          hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {}
+          hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {
+        if (TIMED && STAGE != kStageDeriv && a.ham == kHTimed) {
+            // the stages evaluate H at t_n, t_n + dt and t_n + dt/2; st[par] holds t_n for
+            // the whole step (the step's new record goes to st[par ^ 1])
+            const double tn = a.st[a.par].t;
+            const double ts = STAGE == kStageMid ? tn + dt : STAGE == kStageLast ? tn + 0.5 * dt : tn;
+            cos_wt = T(cos(a.hpD[2] * ts));
+        }
+    }
 
     // Example 3.13's curvature term N / (1 + phi_x^2 + phi_y^2) of the stage input,
     // N = (1 + phi_y^2) phi_xx - 2 phi_x phi_y phi_xy + (1 + phi_x^2) phi_yy, from central
@@ -964,25 +995,38 @@ struct Finisher {
                (dim == 2 && a.bcy == kBcDirichlet && (j < 3 || j >= a.ny - 3));
     }
 
-    // Whether a held layer or the curvature term can occur: uniform over the launch, so
-    // callers pick node<true> or node<false> once, outside their loops over nodes, and
-    // the common case carries neither test.
+    // Whether a held layer or the curvature term can occur.
     __host__ __device__ bool extended() const {
         return a.bcx == kBcDirichlet ||
                (dim == 2 && (a.bcy == kBcDirichlet || a.ham == kHCurvature));
     }
 
+    // The node variant of this launch, uniform over it: callers pick it once, outside
+    // their loops over nodes.  The common case carries no test of held layers or the
+    // curvature term.
+    __host__ __device__ int mode() const {
+        return TIMED && a.ham == kHTimed ? kNodeTimed : extended() ? kNodeExtended : kNodePlain;
+    }
+
     __host__ __device__ void operator()(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
-        if (extended())
-            node<true>(col, row, um, up, vm, vp, ps, pn_);
+        const int m = mode();
+        if constexpr (TIMED) {
+            if (m == kNodeTimed) {
+                node<kNodeTimed>(col, row, um, up, vm, vp, ps, pn_);
+                return;
+            }
+        }
+        if (m == kNodeExtended)
+            node<kNodeExtended>(col, row, um, up, vm, vp, ps, pn_);
         else
-            node<false>(col, row, um, up, vm, vp, ps, pn_);
+            node<kNodePlain>(col, row, um, up, vm, vp, ps, pn_);
     }
 
     // ps: the stage input at the node (phi_1 in the second stage, phi_2 in the third);
-    // pn: phi^n at the node (second and third stages).  EXT: extended() holds.
-    template <bool EXT>
+    // pn: phi^n at the node (second and third stages).  MODE: mode() of the launch.
+    template <int MODE>
     __host__ __device__ void node(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
+        constexpr bool EXT = MODE != kNodePlain;   // held layers can occur
         const int64_t i = x0 + col, j = y0 + row;
         if (i >= a.nx || j >= a.ny) return;
         const int64_t idx = j * a.nx + i;
@@ -1006,9 +1050,17 @@ struct Finisher {
         // node coordinates, for the position-dependent Hamiltonian only
         const T xn = a.ham == kHControl ? T(a.x0 + double(i) * a.dxD) : T(0);
         const T yn = a.ham == kHControl ? T(a.y0 + double(j) * a.dyD) : T(0);
-        T H = hamiltonian(a.ham, a.hpT, ub, vb, xn, yn);
+        T H;
+        if (MODE == kNodeTimed) {
+            // ps is this stage's own value at the node
+            const T s = mul_rn(a.hpT[0], ub) + mul_rn(a.hpT[1], vb);
+            H = mul_rn(cos_wt, s) + mul_rn(a.hpT[3], T(ps));
+        } else {
+            H = hamiltonian(a.ham, a.hpT, ub, vb, xn, yn);
+        }
         // the curvature term enters the operator as -eps times a part of H
-        if (EXT && dim == 2 && a.ham == kHCurvature) H -= a.hpT[2] * curvature_term(col, row);
+        if (MODE == kNodeExtended && dim == 2 && a.ham == kHCurvature)
+            H -= a.hpT[2] * curvature_term(col, row);
         if (STAGE == kStagePre) {
             reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{H, Dx, Dy};
             lo_u = fmin(lo_u, fmin(um, up));

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libhjw.so")
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 BC_PERIODIC, BC_EXTRAP, BC_DIRICHLET = 0, 1, 2
 FP64, FP32_MIXED, FP32 = 0, 1, 2
-H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE = 0, 1, 2, 3, 4, 5, 6
+H_LINEAR, H_BURGERS, H_NEGCOS, H_NORM, H_QUARTIC, H_CONTROL, H_CURVATURE, H_TIMED = range(8)
 WENO_L, WENO_JP = 0, 1
 OPT_USE_GRAPH = 0
 OPT_KERNEL_EVENTS = 1

@@ -69,6 +69,28 @@ def test_curvature_hamiltonian_validation(dim, bc, params, ok):
     hjw.lib().hjw_grid_destroy(h)
 
 
+def test_timed_family_takes_16_row_tiles():
+    """The time- and phi-dependent family has kernels for 64 x 16 tiles only: 32-row tiles
+    are refused in either order of the two calls."""
+    L = hjw.lib()
+    arr = (ctypes.c_double * 4)(0.8, -0.6, 5.0, 0.9)
+    rc, h = _create(2, [64, 64], [0, 0], [1, 1], [0, 0], hjw.FP64)
+    assert rc == 0
+    assert L.hjw_set_hamiltonian(h, hjw.H_TIMED, arr, 4) == hjw.OK
+    assert L.hjw_set_option(h, hjw.OPT_TILE_ROWS, 32) == hjw.EINVAL
+    assert "16-row" in L.hjw_last_error().decode()
+    assert L.hjw_set_option(h, hjw.OPT_TILE_ROWS, 16) == hjw.OK
+    L.hjw_grid_destroy(h)
+    rc, h = _create(2, [64, 64], [0, 0], [1, 1], [0, 0], hjw.FP64)
+    assert L.hjw_set_option(h, hjw.OPT_TILE_ROWS, 32) == hjw.OK
+    assert L.hjw_set_hamiltonian(h, hjw.H_TIMED, arr, 4) == hjw.EINVAL
+    assert L.hjw_set_hamiltonian(h, hjw.H_BURGERS, arr, 3) == hjw.OK
+    L.hjw_grid_destroy(h)
+    rc, h = _create(1, [64], [0], [1], [0], hjw.FP64)
+    assert L.hjw_set_hamiltonian(h, hjw.H_TIMED, arr, 4) == hjw.OK
+    L.hjw_grid_destroy(h)
+
+
 @pytest.mark.parametrize("bc", [[2, 2], [2, 0], [1, 2]])
 def test_create_accepts_dirichlet(bc):
     rc, h = _create(2, [16, 9], [-1, -1], [1, 1], bc, hjw.FP64)

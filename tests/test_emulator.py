@@ -196,6 +196,25 @@ def test_emulated_curvature_step_matches_oracle(shape, bc, prec, tile_rows):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("shape", [(37,), (160,), (33, 65), (100, 200), (135, 260)])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1), (2, 2), (0, 2)])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_timed_step_matches_oracle(shape, bc, prec, tile_rows):
+    """H(x, t, phi, D phi) = cos(w t)(a u + b v) + lam phi: each stage at its own time (the
+    step starts at t = 0.3) with its own value of phi at the node."""
+    h = tuple(2.0 / n for n in shape[::-1])
+    params = (0.9, -0.6, 5.0, 0.8)
+    phi = W.random_smooth_periodic(shape, seed=sum(shape) + 29)
+    prob = O.Problem(shape, h, O.H_TIMED, params, bc)
+    ref, info = O.rk3_step(prob, phi, 0.3, 1.0, 0.5)
+    rc, got, ei = EM.rk3_step(phi, h, O.H_TIMED, params, 0.3, 1.0, 0.5, bc, prec)
+    assert rc == 0
+    assert ei[0] == info.t
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    tol = {0: 1e-14, 1: 1e-7, 2: 1e-6}[prec]
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
 # --------------------------------------------------------------------------- random sweep
 @pytest.mark.parametrize("seed", range(40))
 def test_emulated_random_configurations_match_oracle(seed):

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from exact_solutions import timed as timed_exact
 from paper_1909_13263_amd import hjw
 from paper_1909_13263_amd import workloads as W
 
@@ -208,3 +209,59 @@ def test_curvature_full_size_steps():
         err = float(np.abs(g.get_phi() - ref).max() / np.abs(ref).max())
         g.close()
         assert err <= tol, (prec, err)
+
+
+# --------------------------------------------------------------------------- H(x, t, phi, D phi)
+TIMED_CASES = [W.timed1d(300, 0.9, 5.0, 0.8, 0.7),
+               W.timed2d(200, 0.8, -0.6, 5.0, 0.9, 0.5, ny=135),
+               dataclasses.replace(W.timed2d(130, 0.8, -0.6, 5.0, 0.9, 0.3, ny=100), bc=W.BC_DIRICHLET),
+               dataclasses.replace(W.timed2d(70, -0.5, 0.7, 3.0, -0.6, 0.4, ny=260), bc=W.BC_EXTRAP)]
+TIMED_IDS = [f"{pr.name}_{'x'.join(map(str, pr.shape))}_bc{pr.bc}" for pr in TIMED_CASES]
+
+
+@pytest.mark.parametrize("k", range(len(TIMED_CASES)), ids=TIMED_IDS)
+def test_timed_whole_solves(k):
+    """The general form of eq. (1.1), H = cos(w t)(a u + b v) + lam phi: every stage at its
+    own time with its own phi, on ragged multi-tile grids and every boundary kind.  FP64
+    within 1e-12 of the oracle, the FP32 paths within their bounds."""
+    pr = TIMED_CASES[k]
+    ref, info = O.step_to(_oracle(pr), pr.phi0(), pr.t_final, pr.cfl)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 2e-6), (FP32, 3e-5)]:
+        phi, gi = _solve(pr, prec)
+        assert gi.t == pr.t_final
+        assert abs(gi.steps - info.steps) <= (0 if prec == FP64 else 1)
+        err = float(np.abs(phi - ref).max() / np.abs(ref).max())
+        print(f"timed {pr.name} {pr.shape} bc={pr.bc} prec={prec} steps={gi.steps} rel={err:.3e}",
+              flush=True)
+        assert err <= tol
+
+
+def test_timed_full_size_matches_the_closed_form():
+    """1024^2 in the benchmark's launch configuration against the equation's own solution
+    exp(-lam t) phi0(x - a S(t), y - b S(t)): the error is the scheme's, far below the
+    solution's scale."""
+    pr = W.timed2d(1024, 0.8, -0.6, 5.0, 0.9, 0.25)
+    exact = timed_exact(pr, pr.t_final)
+    for prec, tol in [(FP64, 1e-8), (MIXED, 2e-6)]:
+        phi, gi = _solve(pr, prec)
+        assert gi.t == pr.t_final
+        err = float(np.abs(phi - exact).max() / np.abs(exact).max())
+        print(f"timed 1024^2 prec={prec} steps={gi.steps} rel. error vs closed form {err:.3e}",
+              flush=True)
+        assert err <= tol
+
+
+def test_timed_requests_through_the_server():
+    """Requests of the time- and phi-dependent family mixed with others in one batch: each
+    result bitwise the single-grid solve (the stage time comes from each request's own
+    record)."""
+    probs = [W.timed2d(130, 0.8, -0.6, 5.0, 0.9, 0.3, ny=100), W.burgers2d(96, 0.1),
+             W.timed2d(64, -0.5, 0.7, 3.0, -0.6, 0.2)]
+    srv = hjw.Server(MIXED, pool_bytes=64 << 20, max_active=8)
+    ids = {srv.submit(pr): pr for pr in probs}
+    results = {r.rid: r for r in srv.drain()}
+    srv.close()
+    for sid, pr in ids.items():
+        ref, _ = _solve(pr, MIXED)
+        assert results[sid].status == hjw.OK
+        assert np.array_equal(results[sid].phi, ref), pr.name

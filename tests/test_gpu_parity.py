@@ -103,6 +103,46 @@ def test_one_rk3_step_matches_oracle(case, prec):
     assert _rel(g.get_phi(), ref) <= STEP_TOL[prec]
 
 
+SPIKES_2D = [(0, 0), (1, 0), (5, 3), (17, 7), (31, 15), (32, 8), (47, 1), (63, 15), (64, 0),
+             (100, 20), (127, 31), (70, 16), (90, 29), (15, 17), (3, 30), (120, 5)]
+SPIKES_1D = [0, 1, 63, 64, 255, 256, 300, 511, 599]
+
+
+@pytest.mark.parametrize("prec", [FP64, MIXED])
+def test_range_fold_finds_the_extreme_anywhere(prec):
+    """The dissipation alpha (eq. LF) is set by the derivative range over the whole grid.
+    A spike at one node makes the derivatives there the extremes; placed at nodes handled
+    by different lanes, rows of lanes, waves and tiles, alpha and dt must follow it."""
+    rel = 1e-12 if prec == FP64 else 1e-5
+    base = W.burgers2d(128, ny=32)
+    for x, y in SPIKES_2D:
+        phi = 0.01 * base.phi0()
+        phi[y, x] += 0.5 + 0.01 * x - 0.003 * y
+        ref, info = O.rk3_step(_oracle_problem(base), phi, 0.0, base.t_final, 0.5)
+        g = hjw.grid_for(base, prec)
+        g.set_phi(phi)
+        gi = g.step_to(base.t_final, 0.5, max_steps=1)
+        g.close()
+        span = max(abs(r) for r in info.range)
+        assert np.allclose(gi.range, info.range, rtol=0, atol=rel * span), (x, y)
+        assert gi.alpha_x == pytest.approx(info.alpha_x, rel=rel), (x, y)
+        assert gi.alpha_y == pytest.approx(info.alpha_y, rel=rel), (x, y)
+        assert gi.last_dt == pytest.approx(info.last_dt, rel=rel), (x, y)
+    base1 = W.burgers1d(600)
+    for x in SPIKES_1D:
+        phi = 0.01 * base1.phi0()
+        phi[x] -= 0.4 + 0.001 * x
+        ref, info = O.rk3_step(_oracle_problem(base1), phi, 0.0, base1.t_final, 0.5)
+        g = hjw.grid_for(base1, prec)
+        g.set_phi(phi)
+        gi = g.step_to(base1.t_final, 0.5, max_steps=1)
+        g.close()
+        span = max(abs(r) for r in info.range[:2])
+        assert np.allclose(gi.range[:2], info.range[:2], rtol=0, atol=rel * span), x
+        assert gi.alpha_x == pytest.approx(info.alpha_x, rel=rel), x
+        assert gi.last_dt == pytest.approx(info.last_dt, rel=rel), x
+
+
 # --------------------------------------------------------------------------- whole solves
 def test_burgers1d_n160_full_solve():
     """Example 3.6's equation, N = 160, CFL 0.5, to t = 0.5/pi^2, FP64: within 1e-12."""
