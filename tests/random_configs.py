@@ -39,3 +39,22 @@ def origin(cfg):
     o = tuple(cfg["lo"][d] + (0.5 * h[d] if cfg["bcs"][d] == W.BC_EXTRAP else 0.0)
               for d in range(len(h)))
     return o + (0.0,) * (2 - len(o))
+
+
+def random_timed_config(seed):
+    """A random configuration of the time- and phi-dependent family (the general form of
+    eq. (1.1)): shape, boundary per axis, (a, b, w, lam), scheme, data and a start time."""
+    rng = np.random.default_rng(10_000 + seed)
+    dim = 2 if rng.random() < 0.75 else 1
+    shape = (int(rng.integers(8, 1200)),) if dim == 1 else \
+        (int(rng.integers(8, 260)), int(rng.integers(8, 260)))
+    bcs = [int(rng.integers(0, 3)) for _ in range(dim)]
+    a, b = rng.uniform(-1.5, 1.5, 2)
+    params = (float(a), float(b) if dim == 2 else 0.0, float(rng.uniform(0.0, 20.0)),
+              float(rng.uniform(-2.0, 2.0)))
+    scheme = int(rng.integers(0, 2))
+    lo = tuple(float(v) for v in rng.uniform(-2.0, 0.0, dim))
+    hi = tuple(l + float(rng.uniform(0.5, 3.0)) for l in lo)
+    phi = 0.5 * W.random_smooth_periodic(shape, seed=seed + 500) + 0.02 * rng.normal(size=shape)
+    return dict(shape=shape, ham=W.H_TIMED, params=params, bcs=tuple(bcs), scheme=scheme,
+                lo=lo, hi=hi, phi=phi, t0=float(rng.uniform(0.0, 3.0)))

@@ -237,3 +237,24 @@ def test_emulated_random_configurations_match_oracle(seed):
     assert rc == 0
     assert ei[1] == pytest.approx(info.last_dt, rel=1e-12)
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), cfg
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_emulated_random_timed_configurations_match_oracle(seed):
+    """Seeded random configurations of H(x, t, phi, D phi) (shape, boundaries, (a, b, w, lam),
+    scheme, start time): one step of the tile code against the oracle."""
+    import random_configs as RC
+    cfg = RC.random_timed_config(seed)
+    h = RC.spacing(cfg)
+    bcs = cfg["bcs"] if len(cfg["shape"]) == 2 else (cfg["bcs"][0], cfg["bcs"][0])
+    prob = O.Problem(cfg["shape"], h, cfg["ham"], cfg["params"], bcs, scheme=cfg["scheme"])
+    ref, info = O.rk3_step(prob, cfg["phi"], cfg["t0"], cfg["t0"] + 1.0, 0.5)
+    EM.set_scheme(cfg["scheme"])
+    try:
+        rc, got, ei = EM.rk3_step(cfg["phi"], h, cfg["ham"], cfg["params"], cfg["t0"],
+                                  cfg["t0"] + 1.0, 0.5, bcs, 0)
+    finally:
+        EM.set_scheme(O.WENO_L)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), cfg["shape"]

@@ -366,6 +366,29 @@ def test_time_kernels_contract():
     g.step_to(0.001, 0.5)
 
 
+@pytest.mark.parametrize("pr", [W.timed2d(200, 0.8, -0.6, 5.0, 0.9, 0.05, ny=135),
+                                W.burgers2d(2048, 0.002)], ids=["timed", "plan_launch"])
+def test_time_kernels_then_solve_is_bitwise_a_fresh_solve(pr):
+    """Timing a grid's kernels (a hold kernel, then repeated launches of each stage) and
+    setting phi again gives the same solve as a grid that was never timed; the family with
+    kernels of its own and a grid that plans in its own launch included."""
+    g = hjw.grid_for(pr, MIXED)
+    g.set_phi(pr.phi0())
+    ms = g.time_kernels(reps=3)
+    assert all(ms[k] > 0 for k in ("pre", "mid", "last")), ms
+    assert (ms["plan"] > 0) == (pr.cells > 2048 * 64 * 16), ms
+    g.set_phi(pr.phi0())
+    gi = g.step_to(pr.t_final, pr.cfl)
+    got = g.get_phi()
+    g.close()
+    f = hjw.grid_for(pr, MIXED)
+    f.set_phi(pr.phi0())
+    fi = f.step_to(pr.t_final, pr.cfl)
+    assert gi.steps == fi.steps
+    assert np.array_equal(got, f.get_phi())
+    f.close()
+
+
 # --------------------------------------------------------------------------- WENO-JP
 JP_SHAPES = [(37,), (1030,), (8, 8), (33, 65), (100, 200), (135, 260), (256, 256)]
 

@@ -45,6 +45,32 @@ def test_random_configuration_one_step(seed):
         assert err <= tol, (seed, prec, err, cfg["shape"], cfg["ham"], cfg["bcs"])
 
 
+@pytest.mark.parametrize("seed", range(20))
+def test_random_timed_configuration_three_steps(seed):
+    """H(x, t, phi, D phi) with random shapes, boundaries, (a, b, w, lam) and schemes: three
+    steps (the later ones at t_n > 0) against the oracle."""
+    cfg = RC.random_timed_config(seed)
+    dim = len(cfg["shape"])
+    bcs = cfg["bcs"] if dim == 2 else (cfg["bcs"][0], cfg["bcs"][0])
+    prob = O.Problem(cfg["shape"], RC.spacing(cfg), cfg["ham"], cfg["params"], bcs,
+                     scheme=cfg["scheme"])
+    ref, info = O.step_to(prob, cfg["phi"], 1.0, 0.5, max_steps=3)
+    scale = np.abs(ref).max()
+    for prec, tol in [(hjw.FP64, 1e-12), (hjw.FP32_MIXED, 2e-6)]:
+        g = hjw.Grid(cfg["shape"], cfg["lo"], cfg["hi"], cfg["bcs"] if dim == 2 else cfg["bcs"][0],
+                     prec)
+        g.set_hamiltonian(cfg["ham"], cfg["params"])
+        if cfg["scheme"]:
+            g.set_scheme(cfg["scheme"])
+        g.set_phi(cfg["phi"])
+        gi = g.step_to(1.0, 0.5, max_steps=3)
+        phi = g.get_phi()
+        g.close()
+        assert gi.steps == info.steps
+        err = float(np.abs(phi - ref).max() / scale)
+        assert err <= tol, (seed, prec, err, cfg["shape"], cfg["params"], cfg["bcs"])
+
+
 def test_random_configurations_through_the_server():
     """The 2-D random configurations submitted together to the batched server (a few
     steps each): each result is bitwise the single-grid result of the same solve."""
