@@ -50,9 +50,9 @@ def kernel_bytes_per_cell(phi_b, flux_b):
 # counters: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
 # counters read for a plain 256 MiB copy kernel.  Valid only for the kernel sources whose
 # SHA-256 is recorded; any change to them turns the figure into null until re-measured.
-MEASURED_TRAFFIC = {"source_sha256": "80f18095e3a4b689a5c5b73a00bc109f83d685531d7d390101cdfdb6d9a09ab4",
+MEASURED_TRAFFIC = {"source_sha256": "fe5fce889bb192cdbcb70bdc927da8dddd814f4f0e48dd44a7aadd932b6c6d94",
                     "n": 1024, "tile_rows": 16,
-                    "bytes": {"pre": 22080000, "mid": 31010000, "last": 26150000}}
+                    "bytes": {"pre": 22140000, "mid": 31030000, "last": 26170000}}
 
 
 def segment(n):
@@ -213,33 +213,39 @@ def accuracy_cases():
 
 
 def solve_once(hjw, pr, prec):
+    """One whole solve; returns (phi, info, node-stages/s of step_to with phi0 resident)."""
+    import torch
     g = hjw.grid_for(pr, prec)
     g.set_phi(pr.phi0())
-    info = g.step_to(pr.t_final, pr.cfl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = g.step_to(pr.t_final, pr.cfl)   # returns once the solve is done
+    wall = time.perf_counter() - t0
     phi = g.get_phi()
     g.close()
-    return phi, info
+    return phi, info, pr.cells * info.steps * 3 / wall
 
 
 def accuracy(hjw):
     """Error of the FP32 paths against FP64 on the same GPU, whose results match the
     FP64 oracle to 1e-12 of max|phi| (the parity tests): L-inf; L1 as the grid mean of
     |error| and as the domain integral dx dy sum|error|; L-inf and mean L1 also relative
-    to max|phi|."""
+    to max|phi|.  Each whole solve's node-stages/s (phi0 resident, step_to timed) rides
+    along: the full-size configurations' throughput in both precisions."""
     out = {}
     for label, pr, precs in accuracy_cases():
-        ref, info = solve_once(hjw, pr, hjw.FP64)
+        ref, info, rate64 = solve_once(hjw, pr, hjw.FP64)
         scale = float(np.abs(ref).max())
-        row = {"fp64_steps": info.steps}
+        row = {"fp64_steps": info.steps, "fp64_cell_updates_per_s": rate64}
         for prec in precs:
-            phi, pinfo = solve_once(hjw, pr, prec)
+            phi, pinfo, rate = solve_once(hjw, pr, prec)
             err = np.abs(phi - ref)
             name = {hjw.FP32_MIXED: "fp32_stencil", hjw.FP32: "fp32_storage"}[prec]
             cell = float(np.prod(pr.spacing))
             row[name] = {"linf": float(err.max()), "l1": float(err.mean()),
                          "l1_integral": float(err.sum()) * cell,
                          "linf_rel": float(err.max()) / scale, "l1_rel": float(err.mean()) / scale,
-                         "steps": pinfo.steps}
+                         "steps": pinfo.steps, "cell_updates_per_s": rate}
         out[label] = row
     return out
 

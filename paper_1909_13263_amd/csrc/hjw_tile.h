@@ -116,8 +116,8 @@ constexpr int kPartialStride = 5;
 __device__ inline float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __host__ inline float rcp_t(float x) { return 1.0f / x; }
 __host__ __device__ inline double rcp_t(double x) { return 1.0 / x; }
-__device__ inline double asinh_t(double x) { return asinh(x); }
-__host__ inline double asinh_t(double x) { return std::asinh(x); }
+__device__ inline double log_t(double x) { return log(x); }
+__host__ inline double log_t(double x) { return std::log(x); }
 __device__ inline float sqrt_t(float x) { return sqrtf(x); }
 __host__ inline float sqrt_t(float x) { return std::sqrt(x); }
 __device__ inline double sqrt_t(double x) { return sqrt(x); }
@@ -181,15 +181,16 @@ __host__ __device__ inline float mean2sq_series(float sg, float dl, float q4, fl
     return mul_rn(q4 * X, X);
 }
 
-// Antiderivative of sqrt(1+s^2): (s sqrt(1+s^2) + asinh s) / 2.
+// Antiderivative of sqrt(1+s^2): (s sqrt(1+s^2) + asinh s) / 2, with
+// asinh s = sign(s) ln(|s| + sqrt(1+s^2)): the logarithm's argument is >= 1 (no
+// cancellation) and the square root serves both terms.  Only pairs with a wide relative
+// gap use it, so that the difference of two values is divided by a gap of at least
+// tau sqrt(4 + sg^2): the rounding is amplified by a small factor only.
 __host__ __device__ inline double prim(double s) {
-    return 0.5 * (s * sqrt_t(1.0 + s * s) + asinh_t(s));
+    const double r = sqrt_t(1.0 + s * s);
+    return 0.5 * (s * r + copysign(log_t(fabs(s) + r), s));
 }
-// FP32: from the hardware square root and base-2 logarithm (about 1 ulp each), with
-// asinh s = sign(s) ln(|s| + sqrt(1+s^2)), whose argument is >= 1 (no cancellation).
-// Only pairs with a wide relative gap use it, so that the difference of two values is
-// divided by a gap of at least tau sqrt(4 + sg^2): the rounding is amplified by a
-// small factor only.
+// FP32: the same from the hardware square root and base-2 logarithm (about 1 ulp each).
 __device__ inline float prim(float s) {
     const float r = __builtin_amdgcn_sqrtf(fmaf(s, s, 1.0f));
     const float l = __builtin_amdgcn_logf(fabsf(s) + r) * 0.693147180559945309f;
