@@ -78,3 +78,36 @@ def test_burgers_1024_fp64_whole_solve_matches_oracle():
     print(f"burgers 1024^2 FP64 whole solve: steps {ginfo.steps}/{info.steps} rel {err:.3e}")
     assert ginfo.steps == info.steps
     assert err <= 1e-12
+
+
+def test_grid_of_more_than_2_31_nodes_is_its_periodic_cell_tiled():
+    """64-bit indexing at the size HBM allows: a periodic 49152 x 49152 grid (2.4e9 nodes,
+    above 2^31; 68 GB of FP32-stencil workspace, plan in its own launch over 2.36 M tiles)
+    holding data of period 1024 in both axes.  Every node sees the stencil values and the
+    derivative box of the 1024 x 1024 grid, so two steps give that grid's result tiled
+    48 x 48, bit for bit; the 1024 x 1024 result matches the oracle (test_gpu_parity.py)."""
+    import torch
+    p, reps = 1024, 48
+    n = p * reps
+    small = W.burgers2d(p, 1.0)
+    g = hjw.grid_for(small, MIXED)
+    g.set_phi(small.phi0())
+    gi = g.step_to(small.t_final, small.cfl, max_steps=2)
+    ref = torch.from_numpy(g.get_phi()).cuda()
+    g.close()
+    lo = small.lo
+    hi = tuple(l + reps * (h - l) for l, h in zip(small.lo, small.hi))
+    big = hjw.Grid((n, n), lo, hi, hjw.BC_PERIODIC, MIXED)
+    big.set_hamiltonian(small.ham, small.params)
+    phi = torch.from_numpy(small.phi0()).cuda().repeat(reps, reps)   # 19 GB, FP64
+    big.set_phi(phi)
+    bi = big.step_to(small.t_final, small.cfl, max_steps=2)
+    big.get_phi_device(out=phi)
+    big.close()
+    assert bi.steps == gi.steps == 2
+    assert bi.last_dt == gi.last_dt and bi.alpha_x == gi.alpha_x and bi.range == gi.range
+    blocks = phi.view(reps, p, reps, p)
+    for r in range(reps):
+        assert torch.equal(blocks[r], ref[:, None, :].expand(p, reps, p)), r
+    del phi, blocks
+    torch.cuda.empty_cache()
