@@ -684,12 +684,11 @@ hjw_status hjw_time_kernels(hjw_grid* g, int reps, double* ms) {
                        std::numeric_limits<double>::max(), 0.5, limit);
     HIP_TRY(hipGetLastError());
     const bool timing = g->timing;
-    g->timing = false;
-    HIP_TRY(enqueue_step(g));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    hipError_t err = hipSuccess;
+    g->timing = false;   // restored on every path below
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = enqueue_step(g);
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
     g->par ^= 1;   // launch against the records of the step just taken
     const bool plan = plan_launch(g);
     auto launch = [&](int k) {
@@ -727,8 +726,8 @@ hjw_status hjw_time_kernels(hjw_grid* g, int reps, double* ms) {
     }
     g->par ^= 1;
     g->timing = timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     g->phi_set = false;   // phi was overwritten by the repeated third stage
     if (err != hipSuccess) return fail(HJW_EHIP, "kernel timing failed: %s", hipGetErrorString(err));
     HIP_TRY(hipStreamSynchronize(g->stream));
