@@ -265,3 +265,34 @@ def test_timed_requests_through_the_server():
         ref, _ = _solve(pr, MIXED)
         assert results[sid].status == hjw.OK
         assert np.array_equal(results[sid].phi, ref), pr.name
+
+
+def test_timed_without_time_and_decay_is_linear_bitwise():
+    """w = lam = 0 makes the family's own kernels compute a u + b v exactly as the linear
+    Hamiltonian's kernels do: the same bits in every precision."""
+    base = W.timed2d(130, 0.7, -0.3, 0.0, 0.0, 0.1, ny=100)
+    lin = dataclasses.replace(base, ham=W.H_LINEAR, params=(0.7, -0.3))
+    for prec in (FP64, MIXED, FP32):
+        a, ai = _solve(base, prec)
+        b, bi = _solve(lin, prec)
+        assert ai.steps == bi.steps
+        assert np.array_equal(a, b), prec
+
+
+@pytest.mark.parametrize("lam", [0.9, -1.3])
+def test_timed_pure_decay_is_the_rk3_stability_polynomial(lam):
+    """a = b = 0: every step multiplies phi by 1 - z + z^2/2 - z^3/6, z = lam dt (TVD-RK3's
+    stability polynomial), whatever w and t are; FP64 to rounding."""
+    pr = W.timed2d(200, 0.0, 0.0, 7.0, lam, 100.0, ny=70)   # no step is clamped
+    phi0 = pr.phi0() + 2.0
+    g = hjw.grid_for(pr, FP64)
+    g.set_phi(phi0)
+    phi = phi0
+    for _ in range(4):
+        gi = g.step_to(pr.t_final, pr.cfl, max_steps=1)
+        z = lam * gi.last_dt
+        phi = (1.0 - z + z * z / 2.0 - z ** 3 / 6.0) * phi
+        assert gi.last_dt == pytest.approx(pr.cfl / abs(lam), rel=1e-15)
+        got = g.get_phi()
+        assert np.abs(got - phi).max() <= 1e-14 * np.abs(phi).max()
+    g.close()
