@@ -55,7 +55,8 @@ class _Problem(ctypes.Structure):
                 ("ham", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("hp", ctypes.c_double * 4),
                 ("scheme", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("x0", ctypes.c_double), ("y0", ctypes.c_double)]
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("local_lf", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -130,6 +131,7 @@ class Problem:
     bc: object = BC_PERIODIC
     scheme: int = WENO_L
     origin: tuple = (0.0, 0.0)
+    local_lf: bool = False   # alpha per node over its own pair (the other reading; tests only)
     _c: _Problem = field(init=False, repr=False)
 
     def __post_init__(self):
@@ -147,6 +149,7 @@ class Problem:
         p.scheme = int(self.scheme)
         p.x0 = float(self.origin[0])
         p.y0 = float(self.origin[1]) if len(self.origin) > 1 else 0.0
+        p.local_lf = 1 if self.local_lf else 0
         hp = list(self.params) + [0.0] * (4 - len(self.params))
         for k in range(4):
             p.hp[k] = float(hp[k])
