@@ -119,11 +119,18 @@ typedef enum {
                                   automatic, 4 (FP32 stencil, 16-row tiles: 512 threads per
                                   tile) or 8 (256 threads per 16-row tile).  Results are
                                   identical. */
-    HJW_OPT_PLAN = 4           /* where a 2-D step's dissipation and time step are computed:
+    HJW_OPT_PLAN = 4,          /* where a 2-D step's dissipation and time step are computed:
                                   0 (default) automatic, 1 in every workgroup of the second
                                   stage, 2 in a one-wave launch of its own between the first
                                   and second stages (chosen automatically above 2048 tiles).
                                   Results are identical. */
+    HJW_OPT_DISSIPATION = 5    /* alpha of eq. (LF), alpha = max |H_1|, whose range the paper
+                                  leaves open: 0 (default) over the box of the step's
+                                  derivative ranges, held for the step's three stages; 1 per
+                                  node and stage over the node's own box [u-, u+] x [v-, v+]
+                                  (local Lax-Friedrichs; the printed Table 2 follows it).  The
+                                  time step keeps the global alpha.  Not with
+                                  HJW_OPT_TILE_ROWS = 32 (EINVAL). */
 } hjw_option;
 
 typedef struct hjw_grid hjw_grid;

@@ -73,6 +73,7 @@ struct hjw_grid {
     int tile_rows = 16;  // 2-D tile height (16 or 32)
     int seg_opt = 0;     // nodes per thread in the 2-D sweeps: 0 automatic, 4 or 8
     int plan_opt = 0;    // step plan: 0 automatic, 1 in every workgroup, 2 own launch
+    int llf = 0;         // dissipation: 0 the step's global alpha, 1 per node (local LF)
     int scheme = HJW_WENO_L;
 
     // host mirror
@@ -172,6 +173,7 @@ StageArgs<T, P> make_args(const hjw_grid* g) {
     a.y0 = g->y0;
     a.dxD = g->dx;
     a.dyD = g->dy;
+    a.llf = g->llf;
     return a;
 }
 
@@ -190,13 +192,14 @@ template <typename T, typename P, int STAGE>
 hipError_t launch_stage(const hjw_grid* g, StageArgs<T, P> a) {
     const dim3 grid(unsigned(g->nbx * g->nby));
     constexpr bool kNarrow = !std::is_same<T, double>::value;   // the S = 4 kernels
-    // the time- and phi-dependent family has kernels of its own (16-row tiles, 8-node
-    // segments), so that the other families' kernels carry none of its code
+    // the time- and phi-dependent family and the local dissipation have kernels of their
+    // own (16-row tiles, 8-node segments), so that the other kernels carry none of their code
     constexpr bool kH = STAGE != kStageDeriv;   // the derivatives do not evaluate H
-    if (kH && g->ham == HJW_H_TIMED && g->dim == 2)
+    const bool own = g->ham == HJW_H_TIMED || g->llf;
+    if (kH && own && g->dim == 2)
         hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 16, 8, true>), grid, dim3(threads2d(16, 8)),
                            0, g->stream, a);
-    else if (kH && g->ham == HJW_H_TIMED)
+    else if (kH && own)
         hipLaunchKernelGGL((k_stage1d<T, P, STAGE, true>), grid, dim3(256), 0, g->stream, a);
     else if (g->dim == 2 && g->tile_rows == 32)
         hipLaunchKernelGGL((k_stage2d<T, P, STAGE, 32, 8, false>), grid, dim3(threads2d(32, 8)),
@@ -629,6 +632,14 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
         if (!g->use_graph) drop_graph(g);
         return HJW_OK;
     }
+    if (option == HJW_OPT_DISSIPATION) {
+        if (value != 0 && value != 1) return fail(HJW_EINVAL, "dissipation must be 0 or 1");
+        if (value == 1 && g->dim == 2 && g->tile_rows == 32)
+            return fail(HJW_EINVAL, "the local dissipation runs 16-row tiles");
+        g->llf = int(value);
+        drop_graph(g);
+        return HJW_OK;
+    }
     if (option == HJW_OPT_PLAN) {
         if (value < 0 || value > 2) return fail(HJW_EINVAL, "plan option must be 0, 1 or 2");
         g->plan_opt = int(value);
@@ -650,6 +661,8 @@ hjw_status hjw_set_option(hjw_grid* g, int option, int64_t value) {
             return fail(HJW_EINVAL, "32-row tiles take 8-node segments");
         if (value == 32 && g->ham_set && g->ham == HJW_H_TIMED)
             return fail(HJW_EINVAL, "the TIMED family runs 16-row tiles");
+        if (value == 32 && g->llf)
+            return fail(HJW_EINVAL, "the local dissipation runs 16-row tiles");
         g->tile_rows = int(value);
         if (g->dim == 2) g->nby = int((g->ny + g->tile_rows - 1) / g->tile_rows);
         drop_graph(g);

@@ -24,6 +24,7 @@ namespace {
 int g_tile_rows = 32;  // 2-D tile height being emulated (32 or 16)
 int g_segment = 8;     // nodes per thread in the 2-D sweeps (8, or 4 with 16-row tiles)
 int g_scheme = 0;      // kSchemeL or kSchemeJP
+int g_llf = 0;         // the local dissipation (HJW_OPT_DISSIPATION = 1)
 double g_origin[2] = {0.0, 0.0};   // coordinates of node (0, 0)
 constexpr size_t kGuard = 4096;
 
@@ -96,6 +97,7 @@ struct Emu {
         a.epsx = T(weight_eps(g_scheme, pr.dx));
         a.epsy = T(weight_eps(g_scheme, pr.dy));
         a.scheme = g_scheme;
+        a.llf = g_llf;
         a.x0 = g_origin[0];
         a.y0 = g_origin[1];
         a.dxD = pr.dx;
@@ -313,6 +315,13 @@ int hjw_emu_set_tile_rows(int rows) {
 void hjw_emu_set_origin(double x0, double y0) {
     g_origin[0] = x0;
     g_origin[1] = y0;
+}
+
+// Dissipation of the emulated kernels: 0 the step's global alpha, 1 per node (local LF).
+int hjw_emu_set_dissipation(int local) {
+    if (local != 0 && local != 1) return -1;
+    g_llf = local;
+    return 0;
 }
 
 // Scheme of the emulated kernels: 0 WENO-L, 1 WENO-JP.

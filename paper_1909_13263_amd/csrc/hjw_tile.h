@@ -60,7 +60,7 @@ constexpr int kHTimed = 7;       // cos(w t)(a u + b v) + lam phi: depends on t 
 // curvature term; the time- and phi-dependent family (held layers possible).
 constexpr int kNodePlain = 0;
 constexpr int kNodeExtended = 1;
-constexpr int kNodeTimed = 2;
+constexpr int kNodeTimed = 2;   // also every launch with the local dissipation (llf)
 
 // Stage kinds of one Runge-Kutta step.
 constexpr int kStagePre = 0;    // derivatives of phi^n -> Hbar, Dx, Dy, block ranges
@@ -517,6 +517,7 @@ struct StageArgs {
     int scheme;       // kSchemeL or kSchemeJP
     double x0, y0;    // coordinates of node (0, 0)
     double dxD, dyD;  // spacing in FP64
+    int llf;          // nonzero: alpha of eq. (LF) per node over its own pair (local LF)
 };
 
 // Stage input at a node inside the grid.
@@ -1006,7 +1007,9 @@ struct Finisher {
     // their loops over nodes.  The common case carries no test of held layers or the
     // curvature term.
     __host__ __device__ int mode() const {
-        return TIMED && a.ham == kHTimed ? kNodeTimed : extended() ? kNodeExtended : kNodePlain;
+        return TIMED && (a.ham == kHTimed || a.llf) ? kNodeTimed
+               : extended()                          ? kNodeExtended
+                                                     : kNodePlain;
     }
 
     __host__ __device__ void operator()(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
@@ -1052,7 +1055,7 @@ struct Finisher {
         const T xn = a.ham == kHControl ? T(a.x0 + double(i) * a.dxD) : T(0);
         const T yn = a.ham == kHControl ? T(a.y0 + double(j) * a.dyD) : T(0);
         T H;
-        if (MODE == kNodeTimed) {
+        if (MODE == kNodeTimed && a.ham == kHTimed) {
             // ps is this stage's own value at the node
             const T s = mul_rn(a.hpT[0], ub) + mul_rn(a.hpT[1], vb);
             H = mul_rn(cos_wt, s) + mul_rn(a.hpT[3], T(ps));
@@ -1060,10 +1063,23 @@ struct Finisher {
             H = hamiltonian(a.ham, a.hpT, ub, vb, xn, yn);
         }
         // the curvature term enters the operator as -eps times a part of H
-        if (MODE == kNodeExtended && dim == 2 && a.ham == kHCurvature)
+        if (MODE != kNodePlain && dim == 2 && a.ham == kHCurvature)
             H -= a.hpT[2] * curvature_term(col, row);
-        if (STAGE == kStagePre) {
+        // the dissipation: the step's global alpha, or (local LF) the max of |H_1|, |H_2|
+        // over this node's own box [u-, u+] x [v-, v+]
+        double lax = ax, lay = ay;
+        if (MODE == kNodeTimed && a.llf)
+            dissipation(a.ham, a.hpD, dim, double(fmin(um, up)), double(fmax(um, up)),
+                        double(fmin(vm, vp)), double(fmax(vm, vp)), lax, lay);
+        if (STAGE == kStagePre && MODE == kNodeTimed && a.llf) {
+            // alpha is known here: the record holds the whole numerical Hamiltonian (the
+            // second stage subtracts the global alpha times zero)
+            const double r = double(H) - (mul_rn(lax, double(Dx)) + mul_rn(lay, double(Dy)));
+            reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{T(r), T(0), T(0)};
+        } else if (STAGE == kStagePre) {
             reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{H, Dx, Dy};
+        }
+        if (STAGE == kStagePre) {
             lo_u = fmin(lo_u, fmin(um, up));
             hi_u = fmax(hi_u, fmax(um, up));
             lo_v = fmin(lo_v, fmin(vm, vp));
@@ -1072,7 +1088,7 @@ struct Finisher {
             return;
         }
         // L = -(H - (ax Dx + ay Dy)); the sum is symmetric in x and y
-        const T R = H - (mul_rn(T(ax), Dx) + mul_rn(T(ay), Dy));
+        const T R = H - (mul_rn(T(lax), Dx) + mul_rn(T(lay), Dy));
         const double pn = double(pn_);
         double res;
         if (STAGE == kStageMid) {

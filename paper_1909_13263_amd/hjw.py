@@ -25,6 +25,7 @@ OPT_KERNEL_EVENTS = 1
 OPT_TILE_ROWS = 2
 OPT_SEGMENT = 3
 OPT_PLAN = 4
+OPT_DISSIPATION = 5
 KERNEL_NAMES = ("pre", "plan", "mid", "last")
 
 PREC_NAMES = {"fp64": FP64, "fp32_mixed": FP32_MIXED, "fp32": FP32}

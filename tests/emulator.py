@@ -25,6 +25,8 @@ def lib():
         L.hjw_emu_set_tile_rows.argtypes = [ctypes.c_int]
         L.hjw_emu_set_segment.restype = ctypes.c_int
         L.hjw_emu_set_segment.argtypes = [ctypes.c_int]
+        L.hjw_emu_set_dissipation.restype = ctypes.c_int
+        L.hjw_emu_set_dissipation.argtypes = [ctypes.c_int]
         L.hjw_emu_set_scheme.restype = ctypes.c_int
         L.hjw_emu_set_scheme.argtypes = [ctypes.c_int]
         L.hjw_emu_set_origin.restype = None
@@ -38,6 +40,11 @@ def lib():
 
 def set_tile_rows(rows):
     assert lib().hjw_emu_set_tile_rows(int(rows)) == 0
+
+
+def set_dissipation(local):
+    """0: the step's global alpha; 1: alpha per node over its own pair (local LF)."""
+    assert lib().hjw_emu_set_dissipation(int(local)) == 0
 
 
 def set_scheme(scheme):

@@ -69,6 +69,20 @@ def test_curvature_hamiltonian_validation(dim, bc, params, ok):
     hjw.lib().hjw_grid_destroy(h)
 
 
+def test_local_dissipation_option_validation():
+    """HJW_OPT_DISSIPATION takes 0 or 1, and 1 runs 16-row tiles only (either order)."""
+    L = hjw.lib()
+    rc, h = _create(2, [64, 64], [0, 0], [1, 1], [0, 0], hjw.FP64)
+    assert rc == 0
+    assert L.hjw_set_option(h, hjw.OPT_DISSIPATION, 2) == hjw.EINVAL
+    assert L.hjw_set_option(h, hjw.OPT_DISSIPATION, 1) == hjw.OK
+    assert L.hjw_set_option(h, hjw.OPT_TILE_ROWS, 32) == hjw.EINVAL
+    assert L.hjw_set_option(h, hjw.OPT_DISSIPATION, 0) == hjw.OK
+    assert L.hjw_set_option(h, hjw.OPT_TILE_ROWS, 32) == hjw.OK
+    assert L.hjw_set_option(h, hjw.OPT_DISSIPATION, 1) == hjw.EINVAL
+    L.hjw_grid_destroy(h)
+
+
 def test_timed_family_takes_16_row_tiles():
     """The time- and phi-dependent family has kernels for 64 x 16 tiles only: 32-row tiles
     are refused in either order of the two calls."""

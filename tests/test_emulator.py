@@ -258,3 +258,48 @@ def test_emulated_random_timed_configurations_match_oracle(seed):
     assert rc == 0
     assert ei[1] == pytest.approx(info.last_dt, rel=1e-12)
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), cfg["shape"]
+
+
+LLF_CASES = [((160,), O.H_NEGCOS, (1.0, 0.0, 1.0), 0), ((37,), O.H_BURGERS, (1.0, 0.0, 1.0), 1),
+             ((33, 65), O.H_BURGERS, (1.0, 1.0, 1.0), (0, 0)),
+             ((100, 200), O.H_NEGCOS, (1.0, -0.5, 1.0), (0, 2)),
+             ((135, 260), O.H_NORM, (1.0, 0.0), (1, 1)),
+             ((40, 70), O.H_QUARTIC, (0.7, 0.4, 0.1), (2, 2)),
+             ((64, 64), O.H_CURVATURE, (-1.0, 1.0, 0.05), (0, 0)),
+             ((96, 130), O.H_TIMED, (0.9, -0.6, 5.0, 0.8), (0, 1))]
+
+
+@pytest.mark.parametrize("case", range(len(LLF_CASES)))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_local_dissipation_matches_oracle(case, prec):
+    """HJW_OPT_DISSIPATION = 1: alpha per node over its own pair (the reading the printed
+    Table 2 follows), on several families, boundaries and ragged shapes."""
+    shape, ham, params, bc = LLF_CASES[case]
+    h = tuple(2.0 / n for n in shape[::-1])
+    phi = 0.5 * W.random_smooth_periodic(shape, seed=sum(shape) + 41)
+    prob = O.Problem(shape, h, ham, params, bc, local_lf=True)
+    ref, info = O.rk3_step(prob, phi, 0.2, 1.0, 0.5)
+    EM.set_dissipation(1)
+    try:
+        rc, got, ei = EM.rk3_step(phi, h, ham, params, 0.2, 1.0, 0.5, bc, prec)
+    finally:
+        EM.set_dissipation(0)
+    assert rc == 0
+    assert ei[1] == pytest.approx(info.last_dt, rel=1e-12 if prec == 0 else 1e-5)
+    tol = {0: 1e-14, 1: 1e-7, 2: 1e-6}[prec]
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    if prec == 0:   # and it is not the global reading
+        glob, _ = O.rk3_step(O.Problem(shape, h, ham, params, bc), phi, 0.2, 1.0, 0.5)
+        if ham not in (O.H_TIMED,):
+            assert np.abs(glob - ref).max() > 1e3 * tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_emulated_timed_without_time_and_decay_is_linear_bitwise(prec):
+    """w = lam = 0: the tile code of the time- and phi-dependent family computes a u + b v and
+    the RK stages exactly as the linear Hamiltonian's (no contraction in the emulator)."""
+    base = W.timed2d(130, 0.7, -0.3, 0.0, 0.0, 0.1, ny=100)
+    phi = base.phi0()
+    a = EM.rk3_step(phi, base.spacing, O.H_TIMED, base.params, 0.0, 0.1, 0.5, 0, prec)
+    b = EM.rk3_step(phi, base.spacing, O.H_LINEAR, (0.7, -0.3), 0.0, 0.1, 0.5, 0, prec)
+    assert a[0] == b[0] == 0 and np.array_equal(a[1], b[1])

@@ -267,16 +267,19 @@ def test_timed_requests_through_the_server():
         assert np.array_equal(results[sid].phi, ref), pr.name
 
 
-def test_timed_without_time_and_decay_is_linear_bitwise():
-    """w = lam = 0 makes the family's own kernels compute a u + b v exactly as the linear
-    Hamiltonian's kernels do: the same bits in every precision."""
+def test_timed_without_time_and_decay_is_linear_to_rounding():
+    """w = lam = 0 makes the family's own kernels compute a u + b v as the linear
+    Hamiltonian's kernels do.  The two are different kernel instantiations, and the RK
+    combination's products are left to the compiler's fused multiply-adds, which it may
+    form differently in each: the results agree to rounding (the emulated tile code, built
+    without contraction, gives the same bits)."""
     base = W.timed2d(130, 0.7, -0.3, 0.0, 0.0, 0.1, ny=100)
     lin = dataclasses.replace(base, ham=W.H_LINEAR, params=(0.7, -0.3))
-    for prec in (FP64, MIXED, FP32):
+    for prec, tol in ((FP64, 4e-15), (MIXED, 4e-15), (FP32, 4e-7)):
         a, ai = _solve(base, prec)
         b, bi = _solve(lin, prec)
         assert ai.steps == bi.steps
-        assert np.array_equal(a, b), prec
+        assert np.abs(a - b).max() <= tol * np.abs(b).max(), prec
 
 
 @pytest.mark.parametrize("lam", [0.9, -1.3])
@@ -296,3 +299,46 @@ def test_timed_pure_decay_is_the_rk3_stability_polynomial(lam):
         got = g.get_phi()
         assert np.abs(got - phi).max() <= 1e-14 * np.abs(phi).max()
     g.close()
+
+
+# --------------------------------------------------------------------------- local LF
+LLF_GPU = [W.negcos1d(300, 0.3), W.burgers2d(200, 0.05, ny=135),
+           dataclasses.replace(W.negcos2d(130, 0.05, ny=100), bc=W.BC_DIRICHLET),
+           W.levelset2d(100, 0.05, ny=72)]
+
+
+@pytest.mark.parametrize("k", range(len(LLF_GPU)),
+                         ids=[f"{p.name}_{'x'.join(map(str, p.shape))}" for p in LLF_GPU])
+def test_local_dissipation_whole_solves(k):
+    """HJW_OPT_DISSIPATION = 1 (alpha per node over its own pair): whole solves against the
+    oracle's local reading; FP64 within 1e-12, the FP32 paths within their bounds."""
+    pr = LLF_GPU[k]
+    prob = O.Problem(pr.shape, pr.spacing, pr.ham, pr.params, pr.bc, local_lf=True)
+    ref, info = O.step_to(prob, pr.phi0(), pr.t_final, pr.cfl)
+    for prec, tol in [(FP64, 1e-12), (MIXED, 2e-6), (FP32, 3e-5)]:
+        g = hjw.grid_for(pr, prec)
+        g.set_option(hjw.OPT_DISSIPATION, 1)
+        g.set_phi(pr.phi0())
+        gi = g.step_to(pr.t_final, pr.cfl)
+        phi = g.get_phi()
+        g.close()
+        assert abs(gi.steps - info.steps) <= (0 if prec == FP64 else 1)
+        err = float(np.abs(phi - ref).max() / np.abs(ref).max())
+        assert err <= tol, (pr.name, prec, err)
+
+
+def test_table2_reproduced_on_the_gpu_with_the_local_dissipation():
+    """Example 3.2 / Table 2 (phi_t - cos(phi_x+1) = 0, t = 0.5/pi^2) through the C ABI in
+    FP64 with the local dissipation and dt proportional to dx^(5/3): the L-inf errors
+    against the exact solution are the printed ones within 10% at N = 40..320."""
+    import exact_solutions as E
+    printed = {40: 4.98e-05, 80: 4.68e-06, 160: 2.31e-07, 320: 9.21e-09}
+    for n, want in printed.items():
+        pr = W.negcos1d(n, 0.5 / math.pi**2)
+        g = hjw.grid_for(pr, FP64)
+        g.set_option(hjw.OPT_DISSIPATION, 1)
+        g.set_phi(pr.phi0())
+        g.step_to(pr.t_final, 0.6 * pr.spacing[0] ** (2.0 / 3.0))
+        err = float(np.abs(g.get_phi() - E.negcos_1d(pr.coords(0), pr.t_final)).max())
+        g.close()
+        assert want / 1.1 <= err <= want * 1.1, (n, err, want)
