@@ -131,7 +131,7 @@ class Problem:
     bc: object = BC_PERIODIC
     scheme: int = WENO_L
     origin: tuple = (0.0, 0.0)
-    local_lf: bool = False   # alpha per node over its own pair (the other reading; tests only)
+    local_lf: bool = False   # alpha per node over its own pair: the reference for HJW_OPT_DISSIPATION = 1
     _c: _Problem = field(init=False, repr=False)
 
     def __post_init__(self):

@@ -38,8 +38,9 @@
  *     The printed tables tell the readings apart: with this global alpha the 2-D
  *     Tables 3 and 4 are reproduced (within 35%) while the 1-D Table 2 comes out
  *     about 4x too large; with alpha taken per node over its own u-+ (and v-+)
- *     (local_lf, kept only to show this), Table 2 is reproduced within 6% and Tables
- *     3 and 4 come out about 4x too small.  The library follows the global reading.
+ *     (local_lf), Table 2 is reproduced within 6% and Tables 3 and 4 come out about
+ *     4x too small.  The global reading is the default; local_lf is the oracle's
+ *     reference for the library's local dissipation option (HJW_OPT_DISSIPATION = 1).
  *   - dt = cfl / (alpha_x/dx + alpha_y/dy), clamped to t_final - t (the paper
  *     gives only the CFL number; the global alpha also under local_lf).  PARITY
  *     UNPINNED by the paper (a reading).

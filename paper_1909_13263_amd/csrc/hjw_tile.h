@@ -530,7 +530,7 @@ __host__ __device__ inline P node_value(const StageArgs<T, P>& a, int64_t idx, d
         // test is issued late and waited for at once, one memory round trip per node
         const Flux3<T> f = reinterpret_cast<const Flux3<T>*>(a.flux)[idx];
         const double r = double(f.h) - (mul_rn(ax, double(f.dx)) + mul_rn(ay, double(f.dy)));
-        return P(double(a.phi_n[idx]) - dt * r);
+        return P(fma(-dt, r, double(a.phi_n[idx])));
     } else if (STAGE == kStageLast) {
         return a.phi_s[idx];
     } else {
@@ -811,7 +811,7 @@ struct Tile {
                 plus_node(e, r, c);
                 const Flux3<T> f = g.f[j];
                 const double rr = double(f.h) - (mul_rn(ax, double(f.dx)) + mul_rn(ay, double(f.dy)));
-                phiL[r * PW + c] = P(double(g.pn[j]) - dt * rr);
+                phiL[r * PW + c] = P(fma(-dt, rr, double(g.pn[j])));
                 if (e < TY * TX) pnL[e] = g.pn[j];
             }
         }
@@ -1089,12 +1089,16 @@ struct Finisher {
         }
         // L = -(H - (ax Dx + ay Dy)); the sum is symmetric in x and y
         const T R = H - (mul_rn(T(lax), Dx) + mul_rn(T(lay), Dy));
+        // The Shu-Osher combinations as explicit fused multiply-adds: every kernel
+        // instantiation rounds them the same way (left to FMA contraction, the compiler
+        // may fuse them differently in each)
         const double pn = double(pn_);
+        const double euler = fma(-dt, double(R), double(ps));   // ps + dt L
         double res;
         if (STAGE == kStageMid) {
-            res = 0.75 * pn + 0.25 * (double(ps) - dt * double(R));
+            res = fma(0.75, pn, 0.25 * euler);
         } else {
-            res = (1.0 / 3.0) * pn + (2.0 / 3.0) * (double(ps) - dt * double(R));
+            res = fma(1.0 / 3.0, pn, mul_rn(2.0 / 3.0, euler));
         }
         const P outv = EXT && hold ? pn_ : P(res);
         a.out[idx] = outv;
