@@ -96,7 +96,38 @@ def parse():
                     help="requests submitted at once to measure the saturation rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--profile", choices=sorted(PROFILE_PRECS),
+                    help="only run the stage kernels of the --workload on an --n grid in this "
+                         "precision: --profile-steps real steps, then --profile-reps launches of "
+                         "each kernel back to back (a short target for counter collection)")
+    ap.add_argument("--workload", default="burgers2d", choices=sorted(PROFILE_WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=4)
+    ap.add_argument("--profile-reps", type=int, default=20)
     return ap.parse_args()
+
+
+PROFILE_PRECS = {"fp64": 0, "fp32_stencil": 1, "fp32": 2}
+PROFILE_WORKLOADS = {"burgers2d": "burgers2d", "negcos2d": "negcos2d", "levelset2d": "levelset2d"}
+
+
+def profile_target(args):
+    """Stage kernels only, for rocprofv3: a grid of the workload, --profile-steps whole steps
+    from phi0 (every kernel does a step), then hjw_time_kernels' launches of each kernel."""
+    import torch
+
+    from paper_1909_13263_amd import hjw
+    from paper_1909_13263_amd import workloads as W
+    pr = getattr(W, PROFILE_WORKLOADS[args.workload])(args.n)
+    prec = PROFILE_PRECS[args.profile]
+    g = hjw.grid_for(pr, prec)
+    g.set_phi(torch.from_numpy(pr.phi0()).to("cuda"))
+    info = g.step_to(pr.t_final, pr.cfl, max_steps=args.profile_steps)
+    times = g.time_kernels(reps=args.profile_reps)
+    g.close()
+    print(json.dumps({"profile": args.profile, "workload": args.workload, "n": args.n,
+                      "cells": pr.cells, "steps": info.steps, "reps": args.profile_reps,
+                      "kernel_ms": times}))
+    return 0
 
 
 def calibrate_copy():
@@ -152,12 +183,14 @@ def cpu_baseline(pr, seconds):
         if time.perf_counter() - t0 >= seconds or t >= pr.t_final:
             break
     wall = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.threads()   # the OpenMP team the oracle's loops ran on
     out = {"value": pr.cells * 3 * steps / wall, "unit": "cell-updates/s", "cores": cores,
            "kind": "oracle",
            "sample": f"{steps} RK3 steps of the {pr.shape[1]}x{pr.shape[0]} grid from t=0 "
                      f"({wall:.1f} s, FP64 C, OpenMP over grid lines)",
-           "cpu_model": cpu_model()}
+           "cpu_model": cpu_model(),
+           "affinity_cpus": len(os.sched_getaffinity(0)),
+           "online_cpus": os.cpu_count()}
     one = single_core_rate(pr, max(2.0, seconds / 4))
     if one is not None:
         out["single_core_value"] = one
@@ -165,14 +198,27 @@ def cpu_baseline(pr, seconds):
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model name, family/model/stepping, and the
+    clock and cache it reports (virtualised hosts may give only a short model name)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break   # the first processor's block
+                k, _, v = line.partition(":")
+                info[k.strip()] = v.strip()
     except OSError:
-        pass
-    return None
+        return None
+    parts = [info.get("model name", "unknown")]
+    if "cpu family" in info:
+        parts.append(f"family {info['cpu family']} model {info.get('model', '?')} "
+                     f"stepping {info.get('stepping', '?')}")
+    if "cpu MHz" in info:
+        parts.append(f"{float(info['cpu MHz']):.0f} MHz")
+    if "cache size" in info:
+        parts.append(f"cache {info['cache size']}")
+    return ", ".join(parts)
 
 
 def single_core_rate(pr, seconds):
@@ -366,6 +412,8 @@ def main():
     torch.cuda.set_device(0)
     if args.calibrate_copy:
         return calibrate_copy()
+    if args.profile:
+        return profile_target(args)
     pr = W.burgers2d(args.n, 0.5 / math.pi**2)
     phi_dev = torch.from_numpy(pr.phi0()).to("cuda")
     cells = pr.cells

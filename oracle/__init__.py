@@ -105,6 +105,8 @@ def _load():
         lib.orc_rk3_step.restype = ctypes.c_int
         lib.orc_rk3_step.argtypes = [ctypes.POINTER(_Problem), dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.POINTER(_Info)]
+        lib.orc_threads.restype = ctypes.c_int
+        lib.orc_threads.argtypes = []
         lib.orc_step_to.restype = ctypes.c_int
         lib.orc_step_to.argtypes = [ctypes.POINTER(_Problem), dp, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int64, ctypes.POINTER(_Info)]
@@ -299,3 +301,8 @@ def step_to(prob: Problem, phi, t_final, cfl, t0=0.0, max_steps=0):
     if rc != 0:
         raise FloatingPointError(f"orc_step_to returned {rc}")
     return out, _info(ci)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's grid-line loops run on."""
+    return int(_load().orc_threads())

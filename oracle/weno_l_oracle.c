@@ -59,6 +59,7 @@
  *     form and by TVD-RK3's stability polynomial.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -682,4 +683,17 @@ int orc_step_to(const orc_problem *p, double *phi, double t_final, double cfl, i
         ++taken;
     }
     return 0;
+}
+
+/* Threads the grid-line loops use (OpenMP's team size for a parallel region here): what a
+ * timing of the oracle states as its core count. */
+int orc_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }

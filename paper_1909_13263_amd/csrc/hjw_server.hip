@@ -425,16 +425,17 @@ hjw_status admit(hjw_server* s) {
         s->peak = std::max(s->peak, s->in_use);
         const size_t n = size_t(q.cells);
         char* w = s->base + s->heap_off + q.off;
+        // phi0 sits in pageable host memory: a synchronous copy, ordered after the work
+        // already on the stream, leaves no copy of pageable memory in flight
+        HIP_TRY(hipStreamSynchronize(s->stream));
         if (s->prec == HJW_FP32) {
             double* stage = reinterpret_cast<double*>(w + 2 * align256(n * 4));
-            HIP_TRY(hipMemcpyAsync(stage, q.phi0.data(), n * sizeof(double),
-                                   hipMemcpyHostToDevice, s->stream));
+            HIP_TRY(hipMemcpy(stage, q.phi0.data(), n * sizeof(double), hipMemcpyHostToDevice));
             hipLaunchKernelGGL(k_d2f, dim3(256), dim3(256), 0, s->stream, stage,
                                reinterpret_cast<float*>(w), int64_t(n));
             HIP_TRY(hipGetLastError());
         } else {
-            HIP_TRY(hipMemcpyAsync(w, q.phi0.data(), n * sizeof(double), hipMemcpyHostToDevice,
-                                   s->stream));
+            HIP_TRY(hipMemcpy(w, q.phi0.data(), n * sizeof(double), hipMemcpyHostToDevice));
         }
         hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, s->stream, s->d_states + 2 * q.slot,
                            s->d_slots + q.slot, q.r.t_final, q.r.cfl);
@@ -539,8 +540,9 @@ hjw_status retire(hjw_server* s) {
                 HIP_TRY(hipGetLastError());
                 src = stage;
             }
-            HIP_TRY(hipMemcpyAsync(q.result.data(), src, n * sizeof(double),
-                                   hipMemcpyDeviceToHost, s->stream));
+            // the result goes to pageable host memory: synchronous, after the conversion
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            HIP_TRY(hipMemcpy(q.result.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
         }
         q.state = 2;
         s->completed.push_back(id);

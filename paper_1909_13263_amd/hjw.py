@@ -6,8 +6,10 @@ Raises if the library was not built -- there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -69,6 +71,20 @@ class Info:
 
 
 _lib = None
+
+# Grids and servers still open when the interpreter exits are closed by an exit hook,
+# before the interpreter tears its modules down: their pinned host buffers, graphs and
+# events are then released while the HIP runtime is certainly still up.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -161,6 +177,7 @@ class Grid:
             workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
         self._ws = workspace
         s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _live.add(self)
         _check(L.hjw_bind(self._h, ctypes.c_void_p(workspace.data_ptr()),
                           ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(s)))
 
@@ -316,6 +333,7 @@ class Server:
                                        ctypes.c_void_p(s), ctypes.byref(h)))
         self._h = h
         self._shapes = {}
+        _live.add(self)
 
     @staticmethod
     def footprint(problem, prec=FP32_MIXED) -> int:
