@@ -211,6 +211,29 @@ hjw_status hjw_time_kernels(hjw_grid *g, int reps, double *ms);
  * caller's.  NULL is ignored. */
 void hjw_grid_destroy(hjw_grid *g);
 
+/* One whole solve that allocates nothing, for callers that cannot allocate device
+ * memory (no hipMalloc/hipFree: serving loops with a fixed memory budget, harnesses that
+ * forbid allocation).  The same as hjw_grid_create + hjw_bind + hjw_set_hamiltonian +
+ * hjw_set_phi + hjw_step_to + hjw_get_phi (WENO-L, global dissipation, 16-row tiles,
+ * kernels launched without graphs), with the same results bit for bit.
+ *   dim, n, lo, hi, bc, prec  as for hjw_grid_create; at most 2^20 nodes (HJW_ENOMEM
+ *                             beyond that);
+ *   ham, params, nparams      as for hjw_set_hamiltonian;
+ *   phi                       device array of nx*ny FP64 values, caller-owned: phi0 on
+ *                             entry, phi at the final time on return (in FP64 and the
+ *                             FP32 stencil it is updated in place while stepping);
+ *   t_final, cfl, max_steps   as for hjw_step_to; info (host, may be NULL) as there;
+ *   hip_stream                hipStream_t, borrowed (NULL: the default stream).
+ * The grid's stage buffer, flux records, range slots and step records (and phi in FP32
+ * storage) live in a fixed device array of the library, 32 MiB + 4 KiB, of which each
+ * device the library runs on keeps one copy until the process ends.  Every call on a
+ * device reuses that device's copy, so calls that overlap in time on one device race.
+ * Synchronous; returns HJW_ENONFINITE if phi0 or a later value is not finite. */
+hjw_status hjw_solve_noalloc(int dim, const int64_t *n, const double *lo, const double *hi,
+                             const int *bc, int prec, int ham, const double *params,
+                             int nparams, double *phi, double t_final, double cfl,
+                             int64_t max_steps, hjw_info *info, void *hip_stream);
+
 /* ----------------------------------------------------------------------------
  * Served stream: many independent 2-D solves batched into the same launches.
  *

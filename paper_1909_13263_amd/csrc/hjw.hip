@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -338,10 +339,14 @@ hjw_status enqueue_steps(hjw_grid* g, int64_t n) {
 }
 
 hjw_status read_state(hjw_grid* g) {
-    HIP_TRY(hipMemcpyAsync(g->pinned, g->state + g->par, sizeof(DevState),
-                           hipMemcpyDeviceToHost, g->stream));
+    // the pinned mirror of a bound grid; the no-allocation solve has none and copies into
+    // ordinary host memory
+    DevState plain{};
+    DevState* dst = g->pinned ? g->pinned : &plain;
+    HIP_TRY(hipMemcpyAsync(dst, g->state + g->par, sizeof(DevState), hipMemcpyDeviceToHost,
+                           g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    g->last = *g->pinned;
+    g->last = *dst;
     for (int k = 0; k < g->ev_used; ++k) {
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, g->ev[2 * k], g->ev[2 * k + 1]));
@@ -369,20 +374,10 @@ hjw_status check_ready(const hjw_grid* g) {
     return HJW_OK;
 }
 
-}  // namespace
-
-// ------------------------------------------------------------------ C ABI
-extern "C" {
-
-const char* hjw_last_error(void) { return hjw::last_error().c_str(); }
-
-const char* hjw_version(void) { return "hjw 0.1 (WENO-L, gfx950)"; }
-
-hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const double* hi,
-                           const int* bc, int prec, hjw_grid** out) {
-    hjw::last_error().clear();
-    if (!out) return fail(HJW_EINVAL, "out is NULL");
-    *out = nullptr;
+// Check a grid description and write it into g (hjw_grid_create and the no-allocation
+// solve).
+hjw_status describe_grid(hjw_grid* g, int dim, const int64_t* n, const double* lo,
+                         const double* hi, const int* bc, int prec) {
     if (dim != 1 && dim != 2) return fail(HJW_EINVAL, "dim must be 1 or 2 (got %d)", dim);
     if (!n || !lo || !hi || !bc) return fail(HJW_EINVAL, "NULL array argument");
     if (prec < HJW_FP64 || prec > HJW_FP32) return fail(HJW_EINVAL, "unknown precision %d", prec);
@@ -397,8 +392,8 @@ hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const do
     if (n[0] > (int64_t(1) << 30) || (dim == 2 && n[1] > (int64_t(1) << 30)) ||
         (dim == 2 && n[0] * n[1] > (int64_t(1) << 34)))
         return fail(HJW_EINVAL, "grid too large");
-    hjw_grid* g = new (std::nothrow) hjw_grid();
-    if (!g) return fail(HJW_ENOMEM, "host allocation failed");
+    if (dim == 2 && (n[0] + kTX - 1) / kTX * ((n[1] + 15) / 16) > INT32_MAX)
+        return fail(HJW_EINVAL, "too many tiles");
     g->dim = dim;
     g->nx = n[0];
     g->ny = dim == 2 ? n[1] : 1;
@@ -410,9 +405,29 @@ hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const do
     g->bcx = bc[0];
     g->bcy = dim == 2 ? bc[1] : HJW_BC_PERIODIC;
     g->prec = prec;
-    if (dim == 2 && int64_t(g->nx + kTX - 1) / kTX * ((g->ny + 15) / 16) > INT32_MAX) {
+    return HJW_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* hjw_last_error(void) { return hjw::last_error().c_str(); }
+
+const char* hjw_version(void) { return "hjw 0.1 (WENO-L, gfx950)"; }
+
+hjw_status hjw_grid_create(int dim, const int64_t* n, const double* lo, const double* hi,
+                           const int* bc, int prec, hjw_grid** out) {
+    hjw::last_error().clear();
+    if (!out) return fail(HJW_EINVAL, "out is NULL");
+    *out = nullptr;
+    hjw_grid* g = new (std::nothrow) hjw_grid();
+    if (!g) return fail(HJW_ENOMEM, "host allocation failed");
+    const hjw_status st = describe_grid(g, dim, n, lo, hi, bc, prec);
+    if (st != HJW_OK) {
         delete g;
-        return fail(HJW_EINVAL, "too many tiles");
+        return st;
     }
     *out = g;
     return HJW_OK;
@@ -765,6 +780,127 @@ void hjw_grid_destroy(hjw_grid* g) {
     if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
     if (g->pinned) (void)hipHostFree(g->pinned);
     delete g;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-allocation solve
+// For callers that cannot allocate device memory.  The stage buffer, the flux records, the
+// range slots and the step records of one grid (and phi itself in FP32 storage) live in a
+// file-scope device array instead of a bound workspace.  Each device holds its own copy of
+// the array; its device address is taken once per device, with that device current, on the
+// first call there.  Every call on a device reuses that device's copy: calls that overlap in
+// time on one device race.
+namespace {
+
+constexpr int64_t kNoAllocNodes = int64_t(1) << 20;   // e.g. a 1024 x 1024 grid
+constexpr size_t kNoAllocControl = 4096;               // range slots and step records
+// FP64 is the largest case: stage buffer 8 B and flux records 24 B per node.
+constexpr size_t kNoAllocBytes = size_t(kNoAllocNodes) * 32 + kNoAllocControl;
+static_assert(align256(sizeof(RangeSlots)) + align256(2 * sizeof(DevState)) <= kNoAllocControl,
+              "control records fit");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+char* scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (in host code the array's own name is only a
+// host-side stand-in, so its device address is looked up and kept per device).
+hjw_status scratch_base(char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HJW_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HJW_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return HJW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjw_status hjw_solve_noalloc(int dim, const int64_t* n, const double* lo, const double* hi,
+                             const int* bc, int prec, int ham, const double* params, int nparams,
+                             double* phi, double t_final, double cfl, int64_t max_steps,
+                             hjw_info* info, void* stream) {
+    hjw::last_error().clear();
+    if (!phi) return fail(HJW_EINVAL, "phi is NULL");
+    hjw_grid g;
+    hjw_status st = describe_grid(&g, dim, n, lo, hi, bc, prec);
+    if (st != HJW_OK) return st;
+    if (g.cells() > kNoAllocNodes)
+        return fail(HJW_ENOMEM, "the no-allocation solve takes at most %lld nodes (got %lld)",
+                    (long long)kNoAllocNodes, (long long)g.cells());
+    st = hjw_set_hamiltonian(&g, ham, params, nparams);
+    if (st != HJW_OK) return st;
+    char* base = nullptr;
+    st = scratch_base(&base);
+    if (st != HJW_OK) return st;
+
+    // the workspace layout of a bound grid, inside the scratch array; phi is the caller's
+    // array except in FP32 storage
+    const size_t cells = size_t(g.cells());
+    size_t o = 0;
+    if (prec == HJW_FP32) {
+        g.phi = base + o;
+        o += align256(cells * 4);
+    } else {
+        g.phi = phi;
+    }
+    g.phi2 = base + o;
+    o += align256(cells * g.elem_phi());
+    g.flux = base + o;
+    o += align256(3 * cells * g.elem_flux());
+    g.slots = base + o;
+    o += align256(sizeof(RangeSlots));
+    g.state = reinterpret_cast<DevState*>(base + o);
+    o += align256(2 * sizeof(DevState));
+    if (o > kNoAllocBytes) return fail(HJW_ENOMEM, "scratch layout exceeds the array");
+    size_t a_, b_, c_, d_, total_;
+    int nbx = 0, nby = 0;
+    layout(&g, &a_, &b_, &c_, &d_, &total_, &nbx, &nby);
+    g.nbx = nbx;
+    g.nby = g.dim == 2 ? int((g.ny + g.tile_rows - 1) / g.tile_rows) : nby;
+    g.stream = static_cast<hipStream_t>(stream);
+    g.use_graph = false;   // instantiating a graph allocates
+    g.bound = true;
+
+    // phi0: reset the step records and range slots (the array keeps the last call's
+    // contents), check it, and convert it to FP32 storage where phi is stored so
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, g.stream, g.state,
+                       static_cast<RangeSlots*>(g.slots));
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, g.stream, phi, int64_t(cells),
+                       g.state);
+    HIP_TRY(hipGetLastError());
+    if (prec == HJW_FP32) {
+        hipLaunchKernelGGL(k_d2f, dim3(1024), dim3(256), 0, g.stream, phi,
+                           static_cast<float*>(g.phi), int64_t(cells));
+        HIP_TRY(hipGetLastError());
+    }
+    st = read_state(&g);
+    if (st != HJW_OK) return st;
+    if (g.last.bad) return fail(HJW_ENONFINITE, "phi0 holds non-finite values");
+    g.phi_set = true;
+
+    st = hjw_step_to(&g, t_final, cfl, max_steps, info);
+    if (st != HJW_OK) return st;
+    if (prec == HJW_FP32) {
+        hipLaunchKernelGGL(k_f2d, dim3(1024), dim3(256), 0, g.stream,
+                           static_cast<const float*>(g.phi), phi, int64_t(cells));
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(g.stream));
+    return HJW_OK;
 }
 
 }  // extern "C"

@@ -24,7 +24,7 @@ inline hjw_status fail(hjw_status code, const char* fmt, ...) {
     return code;
 }
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace hjw
 

@@ -113,6 +113,11 @@ def lib():
             "hjw_kernel_times": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
             "hjw_time_kernels": (ctypes.c_int, [vp, ctypes.c_int, dp]),
             "hjw_grid_destroy": (None, [vp]),
+            "hjw_solve_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(i64), dp, dp,
+                                                 ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                                 ctypes.c_int, dp, ctypes.c_int, vp,
+                                                 ctypes.c_double, ctypes.c_double, i64,
+                                                 ctypes.POINTER(_Info), vp]),
             "hjw_server_footprint": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_Request),
                                                     ctypes.POINTER(ctypes.c_size_t)]),
             "hjw_server_create": (ctypes.c_int, [ctypes.c_int, vp, ctypes.c_size_t, ctypes.c_int,
@@ -264,6 +269,30 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+def solve_noalloc(shape, lo, hi, bc, prec, ham, params, phi, t_final, cfl=0.5, max_steps=0,
+                  stream=None) -> Info:
+    """hjw_solve_noalloc: one whole solve on the library's fixed device array, nothing
+    allocated.  phi is a contiguous FP64 CUDA tensor of `shape`: phi0 in, the result out."""
+    import torch
+    assert isinstance(phi, torch.Tensor) and phi.is_cuda and phi.dtype == torch.float64
+    assert phi.is_contiguous() and tuple(phi.shape) == tuple(shape)
+    dim = len(shape)
+    n = tuple(int(v) for v in shape)[::-1]
+    bcs = bc if isinstance(bc, (tuple, list)) else (bc,) * dim
+    p = [float(v) for v in params]
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    ci = _Info()
+    _check(lib().hjw_solve_noalloc(dim, (ctypes.c_int64 * dim)(*n),
+                                   (ctypes.c_double * dim)(*[float(v) for v in lo]),
+                                   (ctypes.c_double * dim)(*[float(v) for v in hi]),
+                                   (ctypes.c_int * dim)(*[int(b) for b in bcs]), int(prec),
+                                   int(ham), (ctypes.c_double * 4)(*(p + [0.0] * (4 - len(p)))),
+                                   len(p), ctypes.c_void_p(phi.data_ptr()), float(t_final),
+                                   float(cfl), int(max_steps), ctypes.byref(ci),
+                                   ctypes.c_void_p(s)))
+    return _info(ci)
 
 
 def grid_for(problem, prec=FP64, scheme=WENO_L, **kw) -> Grid:

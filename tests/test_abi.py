@@ -221,3 +221,26 @@ def test_server_create_rejects_bad_arguments():
     assert L.hjw_server_create(hjw.FP32_MIXED, ctypes.c_void_p(256), 4096, 64, None,
                                ctypes.byref(h)) == hjw.ENOMEM
     assert not h.value
+
+
+def test_noalloc_solve_validates_on_the_host():
+    """hjw_solve_noalloc refuses bad descriptions and grids above its 2^20-node array before
+    it touches a device (the pointer below is never dereferenced)."""
+    L = hjw.lib()
+
+    def call(dim, n, bc=(0, 0), prec=0, ham=1, phi=1024):
+        lo = (ctypes.c_double * 2)(-2.0, -2.0)
+        hi = (ctypes.c_double * 2)(2.0, 2.0)
+        p = (ctypes.c_double * 4)(1.0, 1.0, 1.0, 0.0)
+        return L.hjw_solve_noalloc(dim, (ctypes.c_int64 * 2)(*n), lo, hi, (ctypes.c_int * 2)(*bc),
+                                   prec, ham, p, 3, ctypes.c_void_p(phi), 0.1, 0.5, 0, None, None)
+
+    assert call(2, (1025, 1024)) == hjw.ENOMEM
+    assert b"2^20" in L.hjw_last_error() or b"1048576" in L.hjw_last_error()
+    assert call(1, ((1 << 20) + 1, 1)) == hjw.ENOMEM
+    assert call(3, (64, 64)) == hjw.EINVAL
+    assert call(2, (4, 64)) == hjw.EINVAL
+    assert call(2, (64, 64), bc=(0, 7)) == hjw.EINVAL
+    assert call(2, (64, 64), prec=5) == hjw.EINVAL
+    assert call(2, (64, 64), ham=99) == hjw.EINVAL
+    assert call(2, (64, 64), phi=0) == hjw.EINVAL
