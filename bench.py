@@ -8,7 +8,9 @@ fused stages) runs on the GPU, from phi0 already resident in HBM.
 value = cells x RK stages / wall time for the FP32-stencil path (FP64 phi, FP64 time step
 and accumulation); the FP64 path is timed the same way and reported beside it.  The
 roofline object describes the dominant kernel, timed with HIP events on the library's
-stream during an instrumented solve that follows the timed region.  cpu_baseline is the
+stream right after the timed region, against the vector ALU peak (the bound of this path);
+counter-derived traffic and instruction mixes ride along while the kernel sources match the
+ones they were measured on.  cpu_baseline is the
 FP64 oracle on the host cores, on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -27,12 +29,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E, 8 TB/s
-# Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39,322 G lane-slots/s
-# (one lane-operation per lane per clock, packed FP32 not used).
-VALU_PEAK_GSLOTS = 256 * 4 * 16 * 2.4
-# Algorithmic vector work of one node-stage in 2-D: about 200 add/mul/FMA plus 28
-# square roots, logarithms, divisions and reciprocals (6 + 6 + 12 + 4), the latter at
-# quarter rate (4 slots each): 200 + 28 * 4 = 312 lane-slots.
+# Vector ALU issue on gfx950, measured with a throughput probe (issue cycles of one wave64
+# instruction on a SIMD): FP32 add/mul/FMA and 32-bit integer operations 2 cycles (32 lanes
+# a cycle), FP64 operations and FP64 conversions 4 (16 lanes), FP32 transcendentals
+# (reciprocal, square root, logarithm) 8.  One lane-slot is one FP32 lane-operation, so the
+# FP32 peak is 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78,643 G lane-slots/s (the published
+# 157.3 TFLOP/s FP32 vector peak counts an FMA as two flops); the FP64 peak in FP64
+# lane-operations is half of it (the published 78.6 TFLOP/s FP64 vector peak).
+CYCLE_HZ = 2.4e9
+SIMDS = 256 * 4
+FP32_PEAK_GSLOTS = SIMDS * 32 * CYCLE_HZ / 1e9
+FP64_PEAK_GOPS = SIMDS * 16 * CYCLE_HZ / 1e9
+ISSUE_CYCLES = {"f32": 2, "i32": 2, "f64": 4, "cvt": 4, "i64": 4, "trans_f32": 8, "trans_f64": 16,
+                "other": 2}
+# Algorithmic work of one node-stage in 2-D (the operations of Section 2, Steps 2-5, per
+# node, both axes): about 200 add/mul/FMA plus 28 square roots, logarithms, divisions and
+# reciprocals (per axis 3 square roots and 3 logarithms for the arc-length antiderivatives,
+# 6 quotients of the cell lengths, 2 weight reciprocals).  In the FP32 stencil a
+# transcendental takes 4 lane-slots (quarter rate): 200 + 28 * 4 = 312 lane-slots.  The FP64
+# path is priced the same way in FP64 lane-operations.
 ALGO_SLOTS_PER_CELL = 200 + 28 * 4
 METRIC = "cell-updates/s per RK3 stage (FP32 vs FP64, %HBM peak); served p50/p99 latency"
 
@@ -46,13 +61,82 @@ def kernel_bytes_per_cell(phi_b, flux_b):
     }
 
 
-# HBM bytes per launch of the FP32-stencil kernels on the benchmark grid, from rocprofv3
-# counters: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB), the factors being what the same
-# counters read for a plain 256 MiB copy kernel.  Valid only for the kernel sources whose
-# SHA-256 is recorded; any change to them turns the figure into null until re-measured.
-MEASURED_TRAFFIC = {"source_sha256": "663aefb64534659ba604393a3e29cff09e1d4a8af198da0478907b0d0c0887f2",
-                    "n": 1024, "tile_rows": 16,
-                    "bytes": {"pre": 22120000, "mid": 31040000, "last": 26160000}}
+# rocprofv3 counters of the stage kernels (Burgers 2-D, bench.py --profile), per launch:
+# traffic = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB; the factors are what the counters read
+# for a plain 256 MiB copy kernel), and executed VALU instructions per node by class
+# (SQ_INSTS_VALU_* x 64 / nodes).  Valid only while the kernel sources hash to the recorded
+# SHA-256; after any change the counter-derived fields are null until re-measured.
+MEASURED = {
+    "source_sha256": "5fb88eb151e939bc24ee999d92fa06ccaa5dedfb73ddc6ccc6331cb003abe8a3",
+    "runs": {
+        "fp32_stencil/1024": {
+            "pre": {"fetch_kib": 4584.5, "write_kib": 12416.0, "traffic_bytes": 22103049,
+                    "valu_per_node": {"f32": 181.0, "f64": 6.5, "i32": 20.44, "cvt": 4.75, "i64": 10.9, "trans_f32": 13.25, "trans_f64": 0.0, "other": 72.21}},
+            "mid": {"fetch_kib": 11056.0, "write_kib": 8192.1, "traffic_bytes": 31031500,
+                    "valu_per_node": {"f32": 182.0, "f64": 18.31, "i32": 23.19, "cvt": 9.75, "i64": 12.73, "trans_f32": 13.25, "trans_f64": 0.06, "other": 50.4}},
+            "last": {"fetch_kib": 8675.0, "write_kib": 8194.2, "traffic_bytes": 26157312,
+                    "valu_per_node": {"f32": 182.0, "f64": 10.5, "i32": 25.78, "cvt": 5.25, "i64": 11.05, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.98}},
+        },
+        "fp32_stencil/2048": {
+            "pre": {"fetch_kib": 17094.9, "write_kib": 49664.0, "traffic_bytes": 85866202,
+                    "valu_per_node": {"f32": 181.0, "f64": 6.5, "i32": 20.26, "cvt": 4.75, "i64": 10.58, "trans_f32": 13.25, "trans_f64": 0.0, "other": 72.07}},
+            "mid": {"fetch_kib": 42249.5, "write_kib": 32768.0, "traffic_bytes": 120081351,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 21.97, "cvt": 9.75, "i64": 11.96, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.51}},
+            "last": {"fetch_kib": 33462.8, "write_kib": 32770.2, "traffic_bytes": 102088614,
+                    "valu_per_node": {"f32": 182.0, "f64": 10.5, "i32": 25.7, "cvt": 5.25, "i64": 10.41, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.28}},
+        },
+        "fp32_stencil/4096": {
+            "pre": {"fetch_kib": 66715.0, "write_kib": 198656.0, "traffic_bytes": 340056102,
+                    "valu_per_node": {"f32": 181.0, "f64": 6.5, "i32": 20.16, "cvt": 4.75, "i64": 10.42, "trans_f32": 13.25, "trans_f64": 0.0, "other": 72.01}},
+            "mid": {"fetch_kib": 166205.3, "write_kib": 131072.0, "traffic_bytes": 474606199,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 21.8, "cvt": 9.75, "i64": 11.86, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.38}},
+            "last": {"fetch_kib": 132198.4, "write_kib": 131074.2, "traffic_bytes": 404962399,
+                    "valu_per_node": {"f32": 182.0, "f64": 10.5, "i32": 25.66, "cvt": 5.25, "i64": 10.08, "trans_f32": 13.25, "trans_f64": 0.0, "other": 34.92}},
+        },
+        "fp64/1024": {
+            "pre": {"fetch_kib": 4770.5, "write_kib": 24704.0, "traffic_bytes": 35066956,
+                    "valu_per_node": {"f32": 0.25, "f64": 282.75, "i32": 19.19, "cvt": 0.5, "i64": 10.9, "trans_f32": 0.25, "trans_f64": 10.75, "other": 134.33}},
+            "mid": {"fetch_kib": 17707.1, "write_kib": 8192.1, "traffic_bytes": 44652828,
+                    "valu_per_node": {"f32": 0.25, "f64": 295.56, "i32": 20.97, "cvt": 0.5, "i64": 13.53, "trans_f32": 0.25, "trans_f64": 10.81, "other": 89.79}},
+            "last": {"fetch_kib": 8841.5, "write_kib": 8194.2, "traffic_bytes": 26498313,
+                    "valu_per_node": {"f32": 0.25, "f64": 287.75, "i32": 25.03, "cvt": 0.5, "i64": 11.05, "trans_f32": 0.25, "trans_f64": 10.75, "other": 71.85}},
+        },
+    },
+}
+
+
+def measured(prec, n):
+    """The counter record of (precision, grid side) if the kernel sources are unchanged."""
+    if not MEASURED or MEASURED["source_sha256"] != kernel_source_sha():
+        return None
+    return MEASURED["runs"].get(f"{prec}/{n}")
+
+
+def counter_fields(rec, kernel, cells, launch_ms):
+    """Counter-derived fields of one kernel: bytes per launch, executed instructions per
+    node, and the VALU busy fraction (issue cycles at the measured rates over the launch)."""
+    if not rec or kernel not in rec:
+        return {"traffic": None}
+    k = rec[kernel]
+    issue = sum(k["valu_per_node"][c] * ISSUE_CYCLES[c] for c in ISSUE_CYCLES) * cells / 64
+    busy = issue / SIMDS / CYCLE_HZ / (launch_ms * 1e-3)
+    return {"traffic": k["traffic_bytes"],
+            "traffic_GBps": k["traffic_bytes"] / (launch_ms * 1e-3) / 1e9,
+            "executed_valu_per_cell": sum(k["valu_per_node"].values()),
+            "executed_by_class": k["valu_per_node"], "valu_busy_frac": busy}
+
+
+def alu_roofline(kernel, cells, launch_ms, prec, n):
+    """The ALU roofline object of one stage kernel: the method's 312 lane-slots per node
+    over the launch against the vector peak of its precision, with counter fields."""
+    fp64 = prec == "fp64"
+    peak = FP64_PEAK_GOPS if fp64 else FP32_PEAK_GSLOTS
+    achieved = ALGO_SLOTS_PER_CELL * cells / (launch_ms * 1e-3) / 1e9
+    obj = {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": peak,
+           "unit": "G FP64 lane-ops/s" if fp64 else "G lane-slots/s", "frac": achieved / peak,
+           "avg_launch_ms": launch_ms, "algorithmic_slots_per_cell": ALGO_SLOTS_PER_CELL}
+    obj.update(counter_fields(measured(prec, n), kernel.split(",")[2], cells, launch_ms))
+    return obj
 
 
 def segment(n):
@@ -298,7 +382,9 @@ def accuracy(hjw):
 
 def beyond_mall(hjw, W, steps=3):
     """A grid whose working set (phi, stage buffer, flux records: 28 B per node) exceeds
-    the 256 MB Infinity Cache: 4096^2 Burgers, FP32 stencil, whole solves to 0.1/pi^2."""
+    the 256 MB Infinity Cache: 4096^2 Burgers, FP32 stencil, whole solves to 0.1/pi^2, then
+    each stage kernel timed back to back.  Its HBM figures come from the counters (traffic
+    per launch) over the live launch time."""
     import torch
     pr = W.burgers2d(4096, 0.1 / math.pi**2)
     phi_dev = torch.from_numpy(pr.phi0()).to("cuda")
@@ -312,13 +398,29 @@ def beyond_mall(hjw, W, steps=3):
         info = g.step_to(pr.t_final, pr.cfl)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
+    g.set_phi(phi_dev)
+    times = g.time_kernels(reps=20)
     g.close()
     rate = pr.cells * 3 * info.steps / wall
     step_bytes = sum(kernel_bytes_per_cell(8, 4).values()) / 3.0   # per node-stage
+    dom = max(("pre", "mid", "last"), key=lambda k: times[k])
+    roof = alu_roofline(f"k_stage2d<float,double,{dom},16,8>", pr.cells, times[dom],
+                        "fp32_stencil", 4096)
+    rec = measured("fp32_stencil", 4096)
+    hbm = None
+    if rec:
+        # traffic of a whole step from the counters over the three kernels' launch times
+        tb = sum(rec[k]["traffic_bytes"] for k in ("pre", "mid", "last"))
+        tt = sum(times[k] for k in ("pre", "plan", "mid", "last")) * 1e-3
+        hbm = {"step_traffic_bytes": tb, "step_kernel_ms": tt * 1e3,
+               "GBps": tb / tt / 1e9, "frac": tb / tt / 1e9 / HBM_PEAK_GBS,
+               "dominant_kernel_GBps": roof["traffic_GBps"],
+               "dominant_kernel_frac": roof["traffic_GBps"] / HBM_PEAK_GBS}
     return {"grid": "4096x4096 burgers2d, t=0.1/pi^2", "working_set_MB": pr.cells * 28 / 1e6,
             "rk_steps": info.steps, "ms_per_solve": wall * 1e3, "cell_updates_per_s": rate,
             "sustained_GBps": rate * step_bytes / 1e9,
-            "sustained_frac": rate * step_bytes / 1e9 / HBM_PEAK_GBS}
+            "sustained_frac": rate * step_bytes / 1e9 / HBM_PEAK_GBS,
+            "kernel_ms": times, "roofline": roof, "hbm_from_counters": hbm}
 
 
 def families(hjw, W, n):
@@ -435,12 +537,9 @@ def main():
     dom = max(("pre", "mid", "last"), key=lambda k: ktimes[k])
     dom_ms = ktimes[dom]
     bpc = kernel_bytes_per_cell(8, 4)[dom]
-    hbm_gbs = bpc * cells / (dom_ms * 1e-3) / 1e9
-    alu_achieved = ALGO_SLOTS_PER_CELL * cells / (dom_ms * 1e-3) / 1e9
-    traffic = None
-    if (MEASURED_TRAFFIC["source_sha256"] == kernel_source_sha()
-            and args.n == MEASURED_TRAFFIC["n"] and args.tile_rows in (0, MEASURED_TRAFFIC["tile_rows"])):
-        traffic = MEASURED_TRAFFIC["bytes"].get(dom)
+    fabric_gbs = bpc * cells / (dom_ms * 1e-3) / 1e9
+    roofline = alu_roofline(f"k_stage2d<float,double,{dom},16,{segment(args.n)}>", cells, dom_ms,
+                            "fp32_stencil", args.n) if args.tile_rows in (0, 16) else None
     # whole-step compulsory bytes per cell-stage: (8 + 8+8 + 8+8 ... ) averaged over stages
     step_bytes = sum(kernel_bytes_per_cell(8, 4).values())
     sustained = step_bytes * cells * main_res["rk_steps"] * args.steps / main_res["wall"] / 1e9
@@ -463,21 +562,24 @@ def main():
                                "t=0.5/pi^2",
                    "cells": cells, "rk_steps": main_res["rk_steps"],
                    "stages_per_solve": main_res["stages"]},
-        "roofline": {"bound": "alu", "kernel": f"k_stage2d<float,double,{dom},16,{segment(args.n)}>",
-                     "achieved": alu_achieved, "peak": VALU_PEAK_GSLOTS,
-                     "unit": "G lane-slots/s", "frac": alu_achieved / VALU_PEAK_GSLOTS,
-                     "traffic": traffic, "avg_launch_ms": dom_ms,
-                     "algorithmic_slots_per_cell": ALGO_SLOTS_PER_CELL},
-        "hbm": {"kernel_GBps": hbm_gbs, "kernel_frac": hbm_gbs / HBM_PEAK_GBS,
+        "roofline": roofline,
+        "hbm": {"kernel_GBps": fabric_gbs, "kernel_frac": fabric_gbs / HBM_PEAK_GBS,
                 "sustained_GBps": sustained, "sustained_frac": sustained / HBM_PEAK_GBS,
-                "peak_GBps": HBM_PEAK_GBS},
+                "peak_GBps": HBM_PEAK_GBS,
+                "served_from": ("Infinity Cache: the %.0f MB working set fits its 256 MB, so these "
+                                "rates are compulsory bytes over time, not HBM traffic"
+                                % (cells * 28 / 1e6)) if cells * 28 < 256e6 else "HBM"},
         "kernel_ms": ktimes,
     }
     if "fp64" in results:
         r = results["fp64"]
+        d64 = max(("pre", "mid", "last"), key=lambda k: r["kernels"][k])
         line["fp64"] = {"value": r["cell_updates_per_s"], "ms_per_step": r["ms_per_solve"],
                         "rk_steps": r["rk_steps"],
-                        "kernel_ms": r["kernels"]}
+                        "kernel_ms": r["kernels"],
+                        "roofline": alu_roofline(f"k_stage2d<double,double,{d64},16,8>", cells,
+                                                 r["kernels"][d64], "fp64", args.n)
+                        if args.tile_rows in (0, 16) else None}
         line["fp32_speedup_over_fp64"] = main_res["cell_updates_per_s"] / r["cell_updates_per_s"]
     if not args.no_jp:
         # the paper's comparison scheme on the same workload (Jiang-Peng indicators)

@@ -66,7 +66,12 @@ template <typename T>
 __device__ inline T wave_max(T x) { return wave_fold<true>(x); }
 
 __device__ inline bool step_open(const DevState& s) {
-    return s.bad == 0 && s.t < s.t_final && s.steps_left > 0;
+    // the fields are read together, in one round trip (a short-circuit test would read them
+    // one after another)
+    const int bad = s.bad;
+    const double t = s.t, t_final = s.t_final;
+    const int64_t left = s.steps_left;
+    return (bad == 0) & (t < t_final) & (left > 0);
 }
 
 __device__ inline int tile_of_block(int bid, int nb, int remap) {
@@ -257,11 +262,16 @@ __device__ inline bool stage_entry(const StageArgs<T, P>& a, int bid, double& dt
         return true;
     }
     if (STAGE == kStageLast) {
+        // the plan's outcome and values in one round trip: the empty asm keeps the loads of
+        // dt and the dissipation ahead of the test of active
         const DevState& n = a.st[a.par ^ 1];
-        if (!n.active) return false;
-        dt = n.dt;
-        ax = n.alpha_x;
-        ay = n.alpha_y;
+        const int active = n.active;
+        double d = n.dt, x = n.alpha_x, y = n.alpha_y;
+        asm volatile("" : "+v"(d), "+v"(x), "+v"(y));
+        if (!active) return false;
+        dt = d;
+        ax = x;
+        ay = y;
         clear_slots(a, bid);
         return true;
     }

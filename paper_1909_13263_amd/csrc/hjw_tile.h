@@ -132,6 +132,11 @@ __device__ inline double cos_t(double x) { return cos(x); }
 __host__ inline double cos_t(double x) { return std::cos(x); }
 __device__ inline bool any_lane(bool p) { return __any(p ? 1 : 0) != 0; }
 __host__ inline bool any_lane(bool p) { return p; }
+// A value the caller knows to be the same on every lane of the wave (a wave's index, a row
+// of a wave's task): taken from the first lane, so the compiler keeps it, and the index
+// arithmetic built on it, in scalar registers.
+__device__ inline int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__host__ inline int uniform_int(int x) { return x; }
 // Products that are rounded on their own (never fused into an add), so that sums
 // like a*u + b*v are symmetric under exchanging (a,u) and (b,v) bit for bit.
 // (The pragma takes the product out of FMA contraction; __fmul_rn does not.)
@@ -891,11 +896,14 @@ struct Tile {
     __host__ __device__ static void finish_nodes(int t, bool col_half, const T* uL, const T* vm,
                                                  const T* vp, const T* vL, const P* phiL,
                                                  const P* pnL, Fin& fin) {
+        // a wave's threads share seg and the half they belong to: every node row below is
+        // uniform over the wave, and its global row address scalar
         const int col = t % TX;
-        const int seg = t / TX;
+        const int seg = uniform_int(t / TX);
+        const int first = uniform_int(col_half ? 0 : kKeep);
 #pragma unroll
         for (int j = 0; j < kKeep; ++j) {
-            const int row = seg * SY + (col_half ? j : kKeep + j);
+            const int row = seg * SY + first + j;
             const int slot = (seg * kKeep + j) * TX + col;
             const T m = col_half ? vm[j] : vL[slot];
             const T p = col_half ? vp[j] : vL[kVElems / 2 + slot];
@@ -954,6 +962,7 @@ struct Finisher {
     const StageArgs<T, P>& a;
     int64_t x0, y0;
     double dt, ax, ay;
+    T axT, ayT;                 // the dissipation in the stencil precision
     T lo_u, hi_u, lo_v, hi_v;
     bool bad;
     int dim;
@@ -963,7 +972,8 @@ struct Finisher {
 
     __host__ __device__ Finisher(const StageArgs<T, P>& args, int64_t x0_, int64_t y0_,
                                  double dt_, double ax_, double ay_, int dim_)
-        : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), lo_u(T(INFINITY)),
+        : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), axT(T(ax_)), ayT(T(ay_)),
+          lo_u(T(INFINITY)),
           hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {
         if (TIMED && STAGE != kStageDeriv && a.ham == kHTimed) {
             // the stages evaluate H at t_n, t_n + dt and t_n + dt/2; st[par] holds t_n for
@@ -1088,7 +1098,8 @@ struct Finisher {
             return;
         }
         // L = -(H - (ax Dx + ay Dy)); the sum is symmetric in x and y
-        const T R = H - (mul_rn(T(lax), Dx) + mul_rn(T(lay), Dy));
+        const bool local = MODE == kNodeTimed && a.llf;
+        const T R = H - (mul_rn(local ? T(lax) : axT, Dx) + mul_rn(local ? T(lay) : ayT, Dy));
         // The Shu-Osher combinations as explicit fused multiply-adds: every kernel
         // instantiation rounds them the same way (left to FMA contraction, the compiler
         // may fuse them differently in each)

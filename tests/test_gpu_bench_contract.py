@@ -39,3 +39,5 @@ def test_bench_prints_one_json_line_with_the_contract_fields():
         assert k in c, k
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1
     assert "fp64" in d and d["fp64"]["value"] > 0
+    r64 = d["fp64"]["roofline"]
+    assert r64["bound"] == "alu" and 0 < r64["frac"] < 1 and r64["peak"] == r["peak"] / 2
