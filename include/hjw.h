@@ -283,9 +283,16 @@ hjw_status hjw_server_create(int prec, void *dev_pool, size_t pool_bytes, int ma
 hjw_status hjw_server_submit(hjw_server *s, const hjw_request *req, const double *phi0,
                              int64_t *id);
 
-/* Admit, run up to `chunks` chunks of batched steps (each chunk ends with
- * retirement and admission), and return; returns at once when nothing is queued
- * or admitted.  *active and *queued (optional) receive the counts on return. */
+/* Run the stream for `chunks` chunks of batched steps and return.  The server keeps
+ * two chunks queued on its stream while anything is admitted: each of the `chunks`
+ * rounds waits for the oldest queued chunk to end, retires the solves it finished
+ * (their phi is copied out behind the chunk still queued) and admits waiting
+ * requests, so the GPU does not wait for the host between chunks.  A chunk may still
+ * be running on return; the next call continues from it.  When nothing is admitted
+ * on return, every queued chunk and copy has ended and every finished request is
+ * reported by hjw_server_completed; returns at once when nothing is queued or
+ * admitted.  *active (at most max_active) and *queued (optional) receive the counts
+ * on return.  A request's finish time is when its result reached host memory. */
 hjw_status hjw_server_run(hjw_server *s, int chunks, int64_t *active, int64_t *queued);
 
 /* Ids of requests finished (done or failed) since the last call, up to cap. */

@@ -5,11 +5,14 @@
 // kernels of one RK3 step (hjw_kernels.h) launched once over the tiles of all
 // admitted solves: a device-resident table gives each solve's arguments and first
 // tile, and each workgroup finds its solve by binary search.  Each solve keeps its own
-// dissipation and time step; solves past their t_final exit at once.  Between
-// chunks of batched steps the host retires finished solves (phi to host memory,
-// pool space released) and admits waiting requests first-in first-out.  Chunks are
-// replayed from HIP graphs cached by launch size, so admission and retirement only
-// rewrite the table.
+// dissipation and time step; solves past their t_final exit at once.  Chunks of
+// batched steps are replayed from HIP graphs cached by launch size, so admission and
+// retirement only rewrite the table.  The host keeps two chunks queued: while the GPU
+// runs one, the host reads the step records of the one before (copied out at its end),
+// retires the solves it finished (phi copied out behind the running chunk, pool space
+// released at once: every later use of that space is queued after the copy) and
+// admits waiting requests first-in first-out (phi0 copied in through pinned staging),
+// so the GPU does not wait for the host between chunks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -112,6 +115,10 @@ constexpr int kChunkSteps = 8;    // batched steps per chunk (even: replays keep
 constexpr int kTileBucket = 128;  // smallest launch, in tiles
 constexpr size_t kGraphCache = 12;
 constexpr int kTY = 16;
+constexpr int kInFlight = 2;      // chunks queued on the stream at most
+// Bytes of phi0 (or of results) moved through one pinned staging buffer per processing
+// step; more waits for the next step (one solve larger than this always moves alone).
+constexpr size_t kStageCap = size_t(256) << 20;
 
 double seconds_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -160,13 +167,26 @@ struct Req {
     hjw_request r{};
     std::vector<double> phi0;
     double t_submit = 0.0, t_finish = 0.0;
-    int state = 0;  // 0 queued, 1 admitted, 2 finished
+    int state = 0;  // 0 queued, 1 admitted, 2 finished, 3 result being copied out
     hjw_status status = HJW_OK;
     std::vector<double> result;
     hjw_info info{};
     size_t off = 0, bytes = 0;
     int slot = -1, tiles = 0, par0 = 0;
     int64_t cells = 0, steps_seen = 0;
+    int64_t first_chunk = 0;   // the first chunk whose table holds this solve
+    int res_buf = -1;          // pinned staging buffer holding its result (state 3)
+    size_t res_off = 0;
+};
+
+// A pinned host buffer for copies between the pool and host memory that must not wait:
+// reused only after the copies issued from it (marked by its event) have completed.
+struct Staging {
+    char* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    std::vector<int64_t> ids;   // results held (download buffers)
 };
 
 struct GraphEntry {
@@ -238,11 +258,23 @@ struct hjw_server {
     int* d_ngrids = nullptr;
     DevState* d_states = nullptr;   // 2 records per slot
     RangeSlots* d_slots = nullptr;
-    // pinned mirrors
-    char* h_table = nullptr;
-    int* h_tile_start = nullptr;
-    int* h_ngrids = nullptr;
-    DevState* h_states = nullptr;
+    // pinned mirrors of the table, two sets: the host fills one while an upload from the
+    // other may still be in flight
+    char* h_table[2] = {nullptr, nullptr};
+    int* h_tile_start[2] = {nullptr, nullptr};
+    int* h_ngrids[2] = {nullptr, nullptr};
+    hipEvent_t tab_ev[2] = {nullptr, nullptr};
+    bool tab_pending[2] = {false, false};
+    int tab_buf = 0;
+    // step records of every slot, copied out at the end of each chunk (buffer chunk % 2)
+    DevState* h_rec[kInFlight] = {};
+    hipEvent_t rec_ev[kInFlight] = {};
+    std::deque<int64_t> inflight;   // chunks queued on the stream, oldest first
+    int64_t next_chunk = 0;
+    // pinned staging of phi0 uploads and result downloads, alternating by processing step
+    Staging up[2], down[2];
+    int64_t step_no = 0;
+    hipStream_t capture = nullptr;  // graphs are captured here (nothing runs on it)
 
     size_t heap_off = 0, heap_bytes = 0, in_use = 0, peak = 0;
     PoolMap heap;
@@ -318,17 +350,17 @@ StageArgs<T, P> request_args(const hjw_server* s, const Req& q) {
 }
 
 template <typename T, typename P>
-void write_table(hjw_server* s) {
-    StageArgs<T, P>* tab = reinterpret_cast<StageArgs<T, P>*>(s->h_table);
+void write_table(hjw_server* s, int b) {
+    StageArgs<T, P>* tab = reinterpret_cast<StageArgs<T, P>*>(s->h_table[b]);
     int tiles = 0;
     for (size_t g = 0; g < s->active.size(); ++g) {
         const Req& q = s->reqs.at(s->active[g]);
         tab[g] = request_args<T, P>(s, q);
-        s->h_tile_start[g] = tiles;
+        s->h_tile_start[b][g] = tiles;
         tiles += q.tiles;
     }
-    s->h_tile_start[s->active.size()] = tiles;
-    *s->h_ngrids = int(s->active.size());
+    s->h_tile_start[b][s->active.size()] = tiles;
+    *s->h_ngrids[b] = int(s->active.size());
     s->launch_tiles = launch_size(tiles);
 }
 
@@ -337,25 +369,25 @@ void write_table(hjw_server* s) {
 constexpr int kPlanLaunchTiles = 2048;
 
 template <typename T, typename P, int S>
-hipError_t launch_batched_step_s(hjw_server* s, int flip) {
+hipError_t launch_batched_step_s(hjw_server* s, int flip, hipStream_t stream) {
     const StageArgs<T, P>* tab = static_cast<const StageArgs<T, P>*>(s->d_table);
     const dim3 grid(unsigned(s->launch_tiles)), block(threads2d(kTY, S));
     const int plan = s->launch_tiles > kPlanLaunchTiles ? 1 : 0;
-    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre, S>), grid, block, 0, s->stream, tab,
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStagePre, S>), grid, block, 0, stream, tab,
                        s->d_tile_start, s->d_ngrids, flip, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (plan) {
         hipLaunchKernelGGL((k_plan_batch<T, P>), dim3(unsigned(s->max_active)), dim3(64), 0,
-                           s->stream, tab, s->d_ngrids, flip);
+                           stream, tab, s->d_ngrids, flip);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageMid, S>), grid, block, 0, s->stream, tab,
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageMid, S>), grid, block, 0, stream, tab,
                        s->d_tile_start, s->d_ngrids, flip, plan);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageLast, S>), grid, block, 0, s->stream, tab,
+    hipLaunchKernelGGL((k_stage2d_batch<T, P, kStageLast, S>), grid, block, 0, stream, tab,
                        s->d_tile_start, s->d_ngrids, flip, 0);
     return hipGetLastError();
 }
@@ -365,97 +397,167 @@ hipError_t launch_batched_step_s(hjw_server* s, int flip) {
 constexpr int kSmallLaunch = 640;
 
 template <typename T, typename P>
-hipError_t launch_batched_step(hjw_server* s, int flip) {
+hipError_t launch_batched_step(hjw_server* s, int flip, hipStream_t stream) {
     if (!std::is_same<T, double>::value && s->launch_tiles <= kSmallLaunch)
-        return launch_batched_step_s<T, P, std::is_same<T, double>::value ? 8 : 4>(s, flip);
-    return launch_batched_step_s<T, P, 8>(s, flip);
+        return launch_batched_step_s<T, P, std::is_same<T, double>::value ? 8 : 4>(s, flip,
+                                                                                   stream);
+    return launch_batched_step_s<T, P, 8>(s, flip, stream);
 }
 
-hipError_t batched_step(hjw_server* s, int flip) {
+hipError_t batched_step(hjw_server* s, int flip, hipStream_t stream) {
     switch (s->prec) {
     case HJW_FP64:
-        return launch_batched_step<double, double>(s, flip);
+        return launch_batched_step<double, double>(s, flip, stream);
     case HJW_FP32_MIXED:
-        return launch_batched_step<float, double>(s, flip);
+        return launch_batched_step<float, double>(s, flip, stream);
     default:
-        return launch_batched_step<float, float>(s, flip);
+        return launch_batched_step<float, float>(s, flip, stream);
     }
 }
 
-void rebuild_table(hjw_server* s) {
+void rebuild_table(hjw_server* s, int b) {
     switch (s->prec) {
     case HJW_FP64:
-        write_table<double, double>(s);
+        write_table<double, double>(s, b);
         break;
     case HJW_FP32_MIXED:
-        write_table<float, double>(s);
+        write_table<float, double>(s, b);
         break;
     default:
-        write_table<float, float>(s);
+        write_table<float, float>(s, b);
     }
 }
 
+// The table of the solves admitted now, from the pinned mirror not used last time (its
+// previous upload is waited for), queued behind the chunks already on the stream.
 hjw_status upload_table(hjw_server* s) {
-    rebuild_table(s);
+    const int b = s->tab_buf ^= 1;
+    if (s->tab_pending[b]) {
+        HIP_TRY(hipEventSynchronize(s->tab_ev[b]));
+        s->tab_pending[b] = false;
+    }
+    rebuild_table(s, b);
     const size_t ng = s->active.size();
     if (ng)
-        HIP_TRY(hipMemcpyAsync(s->d_table, s->h_table, ng * entry_bytes(s->prec),
+        HIP_TRY(hipMemcpyAsync(s->d_table, s->h_table[b], ng * entry_bytes(s->prec),
                                hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->d_tile_start, s->h_tile_start, (ng + 1) * sizeof(int),
+    HIP_TRY(hipMemcpyAsync(s->d_tile_start, s->h_tile_start[b], (ng + 1) * sizeof(int),
                            hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->d_ngrids, s->h_ngrids, sizeof(int), hipMemcpyHostToDevice,
+    HIP_TRY(hipMemcpyAsync(s->d_ngrids, s->h_ngrids[b], sizeof(int), hipMemcpyHostToDevice,
                            s->stream));
+    HIP_TRY(hipEventRecord(s->tab_ev[b], s->stream));
+    s->tab_pending[b] = true;
     s->table_dirty = false;
     return HJW_OK;
 }
 
-hjw_status admit(hjw_server* s) {
-    bool any = false;
-    while (!s->queue.empty() && !s->free_slots.empty()) {
-        Req& q = s->reqs.at(s->queue.front());
+// Room for `need` bytes in a staging buffer whose copies have completed.
+hjw_status reserve(Staging& b, size_t need) {
+    if (need <= b.cap) return HJW_OK;
+    const size_t cap = std::max(need, std::max(size_t(16) << 20, 2 * b.cap));
+    if (b.p) HIP_TRY(hipHostFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b.p), cap, hipHostMallocDefault) != hipSuccess) {
+        b.p = nullptr;
+        return fail(HJW_ENOMEM, "hipHostMalloc of %zu staging bytes failed", cap);
+    }
+    b.cap = cap;
+    return HJW_OK;
+}
+
+// Results whose copies out have completed move to host memory and are reported
+// finished; with wait, the copies of buffer `only` (or of both, -1) are waited for.
+hjw_status finish_downloads(hjw_server* s, bool wait, int only = -1) {
+    for (int b = 0; b < 2; ++b) {
+        Staging& d = s->down[b];
+        if (!d.pending || (only >= 0 && b != only)) continue;
+        if (wait) {
+            HIP_TRY(hipEventSynchronize(d.ev));
+        } else {
+            const hipError_t e = hipEventQuery(d.ev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return fail(HJW_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+        }
+        const double now = seconds_since(s->t0);
+        for (int64_t id : d.ids) {
+            Req& q = s->reqs.at(id);
+            q.result.resize(size_t(q.cells));
+            std::memcpy(q.result.data(), d.p + q.res_off, size_t(q.cells) * sizeof(double));
+            q.res_buf = -1;
+            q.state = 2;
+            q.t_finish = now;
+            s->completed.push_back(id);
+        }
+        d.ids.clear();
+        d.pending = false;
+    }
+    return HJW_OK;
+}
+
+// Admit waiting requests first-in first-out while a slot, pool space and room in this
+// step's upload staging (kStageCap, or one larger request alone) are free; phi0 is
+// copied in behind the queued chunks.
+hjw_status admit(hjw_server* s, Staging& up) {
+    if (up.pending) {
+        HIP_TRY(hipEventSynchronize(up.ev));
+        up.pending = false;
+    }
+    std::vector<int64_t> take;
+    size_t total = 0;
+    for (int64_t id : s->queue) {
+        Req& q = s->reqs.at(id);
+        const size_t nb = align256(size_t(q.cells) * sizeof(double));
+        if (take.size() >= s->free_slots.size()) break;
+        if (!take.empty() && total + nb > kStageCap) break;   // the next step takes it
         const size_t off = s->heap.alloc(q.bytes);
         if (off == SIZE_MAX) break;  // first in, first out: wait for space
         q.off = off;
+        q.res_off = total;           // its place in the upload staging
+        take.push_back(id);
+        total += nb;
+    }
+    if (take.empty()) return s->table_dirty ? upload_table(s) : HJW_OK;
+    hjw_status st = reserve(up, total);
+    if (st != HJW_OK) {
+        for (int64_t id : take) s->heap.release(s->reqs.at(id).off, s->reqs.at(id).bytes);
+        return st;
+    }
+    for (int64_t id : take) {
+        Req& q = s->reqs.at(id);
+        const size_t n = size_t(q.cells);
+        char* src = up.p + q.res_off;
+        q.res_off = 0;
         q.slot = s->free_slots.back();
         s->free_slots.pop_back();
         q.par0 = s->flip;  // its record 0 is current at the next launch
         q.state = 1;
         q.steps_seen = 0;
+        q.first_chunk = s->next_chunk;
         s->in_use += q.bytes;
         s->peak = std::max(s->peak, s->in_use);
-        const size_t n = size_t(q.cells);
+        std::memcpy(src, q.phi0.data(), n * sizeof(double));
+        std::vector<double>().swap(q.phi0);
         char* w = s->base + s->heap_off + q.off;
-        // phi0 sits in pageable host memory: a synchronous copy, ordered after the work
-        // already on the stream, leaves no copy of pageable memory in flight
-        HIP_TRY(hipStreamSynchronize(s->stream));
         if (s->prec == HJW_FP32) {
             double* stage = reinterpret_cast<double*>(w + 2 * align256(n * 4));
-            HIP_TRY(hipMemcpy(stage, q.phi0.data(), n * sizeof(double), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpyAsync(stage, src, n * sizeof(double), hipMemcpyHostToDevice,
+                                   s->stream));
             hipLaunchKernelGGL(k_d2f, dim3(256), dim3(256), 0, s->stream, stage,
                                reinterpret_cast<float*>(w), int64_t(n));
             HIP_TRY(hipGetLastError());
         } else {
-            HIP_TRY(hipMemcpy(w, q.phi0.data(), n * sizeof(double), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpyAsync(w, src, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
         }
         hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, s->stream, s->d_states + 2 * q.slot,
                            s->d_slots + q.slot, q.r.t_final, q.r.cfl);
         HIP_TRY(hipGetLastError());
         s->active.push_back(q.id);
         s->queue.pop_front();
-        s->table_dirty = true;
-        any = true;
     }
-    if (s->table_dirty) {
-        hjw_status st = upload_table(s);
-        if (st != HJW_OK) return st;
-        any = true;
-    }
-    // the host mirrors and phi0 buffers are reused only after their copies are done
-    if (any) {
-        HIP_TRY(hipStreamSynchronize(s->stream));
-        for (int64_t id : s->active) std::vector<double>().swap(s->reqs.at(id).phi0);
-    }
-    return HJW_OK;
+    HIP_TRY(hipEventRecord(up.ev, s->stream));
+    up.pending = true;
+    return upload_table(s);
 }
 
 void drop_graphs(hjw_server* s) {
@@ -463,8 +565,9 @@ void drop_graphs(hjw_server* s) {
     s->graphs.clear();
 }
 
-hjw_status run_chunk(hjw_server* s) {
-    // a cached graph of kChunkSteps batched steps for this launch size and parity
+// Queue one chunk (a cached graph of kChunkSteps batched steps for this launch size and
+// parity) and the copy of every slot's step records behind it.
+hjw_status launch_chunk(hjw_server* s) {
     GraphEntry* ge = nullptr;
     for (auto& g : s->graphs)
         if (g.tiles == s->launch_tiles && g.flip == s->flip) ge = &g;
@@ -478,11 +581,12 @@ hjw_status run_chunk(hjw_server* s) {
             s->graphs.erase(lru);
         }
         hipGraph_t graph = nullptr;
-        HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed));
+        HIP_TRY(hipStreamBeginCapture(s->capture, hipStreamCaptureModeRelaxed));
         hipError_t e = hipSuccess;
         int f = s->flip;
-        for (int k = 0; k < kChunkSteps && e == hipSuccess; ++k, f ^= 1) e = batched_step(s, f);
-        const hipError_t e2 = hipStreamEndCapture(s->stream, &graph);
+        for (int k = 0; k < kChunkSteps && e == hipSuccess; ++k, f ^= 1)
+            e = batched_step(s, f, s->capture);
+        const hipError_t e2 = hipStreamEndCapture(s->capture, &graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             return fail(HJW_EHIP, "batched graph capture failed: %s / %s", hipGetErrorString(e),
@@ -497,30 +601,53 @@ hjw_status run_chunk(hjw_server* s) {
         ge = &s->graphs.back();
     }
     ge->used = ++s->use_clock;
+    const int64_t c = s->next_chunk++;
+    const int b = int(c % kInFlight);
     HIP_TRY(hipGraphLaunch(ge->exec, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->h_rec[b], s->d_states, 2 * size_t(s->max_active) * sizeof(DevState),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipEventRecord(s->rec_ev[b], s->stream));
+    s->inflight.push_back(c);
     s->stats.batched_steps += kChunkSteps;  // kChunkSteps is even: the parity is unchanged
     return HJW_OK;
 }
 
-hjw_status retire(hjw_server* s) {
-    const size_t nrec = 2 * size_t(s->max_active);
-    HIP_TRY(hipMemcpyAsync(s->h_states, s->d_states, nrec * sizeof(DevState),
-                           hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    std::vector<int64_t> keep;
+// The oldest queued chunk has ended: read its step records, retire the solves it
+// finished (their phi copied out behind the chunks still queued, their pool space and
+// slot free at once: whatever reuses them is queued after that copy) and admit.
+// Solves admitted after that chunk was queued have no record in it yet.
+hjw_status process_chunk(hjw_server* s) {
+    const int64_t c = s->inflight.front();
+    s->inflight.pop_front();
+    const DevState* rec_all = s->h_rec[c % kInFlight];
+    HIP_TRY(hipEventSynchronize(s->rec_ev[c % kInFlight]));
+    hjw_status st = finish_downloads(s, false);
+    if (st != HJW_OK) return st;
+    const int b = int(s->step_no++ & 1);
+    Staging& down = s->down[b];
+    st = finish_downloads(s, true, b);
+    if (st != HJW_OK) return st;
+    // which solves retire now: every failed one, and finished ones while their results
+    // fit one staging buffer (kStageCap, or one larger result alone); the others retire
+    // at the next step (their steps are closed, so the chunks between change nothing)
+    std::vector<int64_t> keep, out;
     keep.reserve(s->active.size());
-    bool any = false;
+    size_t total = 0;
     for (int64_t id : s->active) {
         Req& q = s->reqs.at(id);
-        const DevState& rec = s->h_states[2 * q.slot + (q.par0 ^ s->flip)];
-        s->stats.node_stages += 3.0 * double(q.cells) * double(rec.steps - q.steps_seen);
-        q.steps_seen = rec.steps;
-        const bool bad = rec.bad != 0;
-        if (!bad && rec.t < q.r.t_final) {
+        if (q.first_chunk > c) {
             keep.push_back(id);
             continue;
         }
-        any = true;
+        const DevState& rec = rec_all[2 * q.slot + (q.par0 ^ s->flip)];
+        s->stats.node_stages += 3.0 * double(q.cells) * double(rec.steps - q.steps_seen);
+        q.steps_seen = rec.steps;
+        const bool bad = rec.bad != 0;
+        const size_t nb = align256(size_t(q.cells) * sizeof(double));
+        if ((!bad && rec.t < q.r.t_final) || (!bad && total > 0 && total + nb > kStageCap)) {
+            keep.push_back(id);
+            continue;
+        }
         q.info.steps = rec.steps;
         q.info.t = rec.t;
         q.info.last_dt = rec.dt;
@@ -528,10 +655,24 @@ hjw_status retire(hjw_server* s) {
         q.info.alpha_y = rec.alpha_y;
         for (int k = 0; k < 4; ++k) q.info.range[k] = rec.range[k];
         q.status = bad ? HJW_ENONFINITE : HJW_OK;
+        if (!bad) {
+            q.res_off = total;
+            total += nb;
+        }
+        out.push_back(id);
+    }
+    st = reserve(down, total);
+    if (st != HJW_OK) return st;
+    for (int64_t id : out) {
+        Req& q = s->reqs.at(id);
         const size_t n = size_t(q.cells);
         char* w = s->base + s->heap_off + q.off;
-        if (!bad) {
-            q.result.resize(n);
+        if (q.status != HJW_OK) {
+            q.state = 2;
+            q.t_finish = seconds_since(s->t0);
+            s->completed.push_back(id);
+            s->stats.failed += 1;
+        } else {
             const void* src = w;
             if (s->prec == HJW_FP32) {
                 double* stage = reinterpret_cast<double*>(w + 2 * align256(n * 4));
@@ -540,33 +681,25 @@ hjw_status retire(hjw_server* s) {
                 HIP_TRY(hipGetLastError());
                 src = stage;
             }
-            // the result goes to pageable host memory: synchronous, after the conversion
-            HIP_TRY(hipStreamSynchronize(s->stream));
-            HIP_TRY(hipMemcpy(q.result.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
-        }
-        q.state = 2;
-        s->completed.push_back(id);
-        if (bad)
-            s->stats.failed += 1;
-        else
+            HIP_TRY(hipMemcpyAsync(down.p + q.res_off, src, n * sizeof(double),
+                                   hipMemcpyDeviceToHost, s->stream));
+            q.state = 3;
+            q.res_buf = b;
+            down.ids.push_back(id);
             s->stats.done += 1;
-    }
-    if (any) {
-        HIP_TRY(hipStreamSynchronize(s->stream));  // results copied before space is reused
-        const double now = seconds_since(s->t0);
-        for (int64_t id : s->active) {
-            Req& q = s->reqs.at(id);
-            if (q.state != 2) continue;
-            q.t_finish = now;
-            s->heap.release(q.off, q.bytes);
-            s->in_use -= q.bytes;
-            s->free_slots.push_back(q.slot);
-            q.slot = -1;
         }
-        s->active.swap(keep);
+        s->heap.release(q.off, q.bytes);
+        s->in_use -= q.bytes;
+        s->free_slots.push_back(q.slot);
+        q.slot = -1;
         s->table_dirty = true;
     }
-    return HJW_OK;
+    if (!down.ids.empty()) {
+        HIP_TRY(hipEventRecord(down.ev, s->stream));
+        down.pending = true;
+    }
+    s->active.swap(keep);
+    return admit(s, s->up[b]);
 }
 
 }  // namespace
@@ -623,21 +756,32 @@ hjw_status hjw_server_create(int prec, void* pool, size_t pool_bytes, int max_ac
         if (hipStreamCreate(&s->stream) != hipSuccess) st = fail(HJW_EHIP, "hipStreamCreate failed");
         s->own_stream = true;
     }
-    if (st == HJW_OK &&
-        (hipHostMalloc(reinterpret_cast<void**>(&s->h_table), size_t(max_active) * entry_bytes(prec),
-                       hipHostMallocDefault) != hipSuccess ||
-         hipHostMalloc(reinterpret_cast<void**>(&s->h_tile_start), size_t(max_active + 1) * sizeof(int),
-                       hipHostMallocDefault) != hipSuccess ||
-         hipHostMalloc(reinterpret_cast<void**>(&s->h_ngrids), sizeof(int), hipHostMallocDefault) !=
-             hipSuccess ||
-         hipHostMalloc(reinterpret_cast<void**>(&s->h_states), 2 * size_t(max_active) * sizeof(DevState),
-                       hipHostMallocDefault) != hipSuccess))
-        st = fail(HJW_EHIP, "hipHostMalloc failed");
-    if (st == HJW_OK) {
-        *s->h_ngrids = 0;
-        s->h_tile_start[0] = 0;
-        st = upload_table(s);
+    if (st == HJW_OK && hipStreamCreate(&s->capture) != hipSuccess) {
+        s->capture = nullptr;
+        st = fail(HJW_EHIP, "hipStreamCreate failed");
     }
+    auto pinned = [](void* p, size_t bytes) {
+        return hipHostMalloc(reinterpret_cast<void**>(p), bytes, hipHostMallocDefault) ==
+               hipSuccess;
+    };
+    auto event = [](hipEvent_t* e) {
+        return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    };
+    for (int b = 0; b < 2 && st == HJW_OK; ++b) {
+        if (!pinned(&s->h_table[b], size_t(max_active) * entry_bytes(prec)) ||
+            !pinned(&s->h_tile_start[b], size_t(max_active + 1) * sizeof(int)) ||
+            !pinned(&s->h_ngrids[b], sizeof(int)))
+            st = fail(HJW_EHIP, "hipHostMalloc failed");
+        else if (!event(&s->tab_ev[b]) || !event(&s->up[b].ev) || !event(&s->down[b].ev))
+            st = fail(HJW_EHIP, "hipEventCreate failed");
+    }
+    for (int b = 0; b < kInFlight && st == HJW_OK; ++b) {
+        if (!pinned(&s->h_rec[b], 2 * size_t(max_active) * sizeof(DevState)))
+            st = fail(HJW_EHIP, "hipHostMalloc failed");
+        else if (!event(&s->rec_ev[b]))
+            st = fail(HJW_EHIP, "hipEventCreate failed");
+    }
+    if (st == HJW_OK) st = upload_table(s);
     if (st == HJW_OK && hipStreamSynchronize(s->stream) != hipSuccess)
         st = fail(HJW_EHIP, "hipStreamSynchronize failed");
     if (st != HJW_OK) {
@@ -678,12 +822,18 @@ hjw_status hjw_server_submit(hjw_server* s, const hjw_request* req, const double
 
 hjw_status hjw_server_run(hjw_server* s, int chunks, int64_t* active, int64_t* queued) {
     if (!s) return fail(HJW_EINVAL, "NULL server");
-    hjw_status st = admit(s);
-    for (int c = 0; st == HJW_OK && c < chunks && !s->active.empty(); ++c) {
-        st = run_chunk(s);
-        if (st == HJW_OK) st = retire(s);
-        if (st == HJW_OK) st = admit(s);
+    hjw_status st = HJW_OK;
+    if (s->inflight.empty()) st = admit(s, s->up[s->step_no & 1]);
+    for (int c = 0; st == HJW_OK && c < chunks && !(s->active.empty() && s->inflight.empty());
+         ++c) {
+        // keep kInFlight chunks queued while anything is admitted, then wait for the oldest
+        while (st == HJW_OK && !s->active.empty() && int(s->inflight.size()) < kInFlight)
+            st = launch_chunk(s);
+        if (st == HJW_OK) st = process_chunk(s);
     }
+    // with nothing admitted, let the queued chunks end and every result reach host memory
+    while (st == HJW_OK && s->active.empty() && !s->inflight.empty()) st = process_chunk(s);
+    if (st == HJW_OK && s->active.empty()) st = finish_downloads(s, true);
     if (active) *active = int64_t(s->active.size());
     if (queued) *queued = int64_t(s->queue.size());
     return st;
@@ -731,10 +881,27 @@ void hjw_server_destroy(hjw_server* s) {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     drop_graphs(s);
-    if (s->h_table) (void)hipHostFree(s->h_table);
-    if (s->h_tile_start) (void)hipHostFree(s->h_tile_start);
-    if (s->h_ngrids) (void)hipHostFree(s->h_ngrids);
-    if (s->h_states) (void)hipHostFree(s->h_states);
+    auto unpin = [](void* p) {
+        if (p) (void)hipHostFree(p);
+    };
+    auto drop = [](hipEvent_t e) {
+        if (e) (void)hipEventDestroy(e);
+    };
+    for (int b = 0; b < 2; ++b) {
+        unpin(s->h_table[b]);
+        unpin(s->h_tile_start[b]);
+        unpin(s->h_ngrids[b]);
+        unpin(s->up[b].p);
+        unpin(s->down[b].p);
+        drop(s->tab_ev[b]);
+        drop(s->up[b].ev);
+        drop(s->down[b].ev);
+    }
+    for (int b = 0; b < kInFlight; ++b) {
+        unpin(s->h_rec[b]);
+        drop(s->rec_ev[b]);
+    }
+    if (s->capture) (void)hipStreamDestroy(s->capture);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }

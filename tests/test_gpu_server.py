@@ -230,3 +230,38 @@ def test_mixed_schemes_in_one_batch():
         g.close()
         assert results[sid].status == hjw.OK
         assert np.array_equal(results[sid].phi, ref), (pr.name, pr.shape, sc)
+
+
+def test_bursts_larger_than_one_staging_step():
+    """Forty 1200^2 solves (11.5 MB of phi0 and of result each, 460 MB in all) submitted at
+    once: admission and retirement move at most 256 MiB through pinned staging per step, so
+    the burst is admitted over two steps, and the two groups (long horizons first, short
+    ones second) finish in the same chunk and retire over two steps.  Every result is the
+    single-grid result of its own phi0, bit for bit."""
+    n = 1200
+    reqs = []
+    for k in range(40):
+        pr = W.burgers2d(n, 0.004 if k < 23 else 0.001)
+        reqs.append((pr, pr.phi0() * (1.0 + 0.01 * k)))
+    big = hjw.Server.footprint(reqs[0][0], MIXED)
+    srv = hjw.Server(MIXED, pool_bytes=41 * big, max_active=64)
+    ids = {srv.submit(pr, phi0): k for k, (pr, phi0) in enumerate(reqs)}
+    results = {}
+    while True:
+        act, que = srv.run(1)
+        for sid in srv.completed():
+            results[ids[sid]] = srv.result(sid)
+        if act == 0 and que == 0:
+            break
+    st = srv.stats()
+    srv.close()
+    assert len(results) == len(reqs) and st["done"] == len(reqs) and st["pool_in_use"] == 0
+    for k, (pr, phi0) in enumerate(reqs):
+        g = hjw.grid_for(pr, MIXED)
+        g.set_phi(phi0)
+        info = g.step_to(pr.t_final, pr.cfl)
+        ref = g.get_phi()
+        g.close()
+        res = results[k]
+        assert res.status == hjw.OK and res.info.steps == info.steps and res.info.t == info.t
+        assert np.array_equal(res.phi, ref), (k, np.abs(res.phi - ref).max())
