@@ -16,6 +16,7 @@
 // exit at once.
 #pragma once
 
+#include <climits>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,19 +30,24 @@ namespace hjw {
 // ------------------------------------------------------------------ kernels
 // Wave-wide min/max with DPP lane moves (no LDS round trip per step): two quad
 // permutations, then the half-row and row mirrors, leave every lane of each 16-lane row
-// with that row's fold; the four rows' values are read out with readlane.  The result
-// is uniform over the wave.  All 64 lanes must be active.
-template <int CTRL>
+// with that row's fold; two row broadcasts (lane 15 into rows 1 and 3, then lane 31 into
+// rows 2 and 3) carry the folds of rows 0-2 into row 3, whose last lane holds the wave's
+// fold; it is read out with readlane, so the result is uniform over the wave.  The moves
+// leave the lanes they do not write undefined (rows outside a broadcast's mask hold
+// values no later step reads), which lets the compiler fuse each move into the min/max
+// that uses it.  All 64 lanes must be active.
+template <int CTRL, int ROWS = 0xF>
 __device__ inline int dpp_move(int x) {
-    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, CTRL, ROWS, 0xF, false);
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ inline float dpp_move(float x) {
-    return __int_as_float(dpp_move<CTRL>(__float_as_int(x)));
+    return __int_as_float(dpp_move<CTRL, ROWS>(__float_as_int(x)));
 }
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ inline double dpp_move(double x) {
-    const int lo = dpp_move<CTRL>(__double2loint(x)), hi = dpp_move<CTRL>(__double2hiint(x));
+    const int lo = dpp_move<CTRL, ROWS>(__double2loint(x));
+    const int hi = dpp_move<CTRL, ROWS>(__double2hiint(x));
     return __hiloint2double(hi, lo);
 }
 __device__ inline float read_lane(float x, int l) {
@@ -54,11 +60,40 @@ __device__ inline double read_lane(double x, int l) {
 template <bool MAX, typename T>
 __device__ inline T wave_fold(T x) {
     const auto f = [](T p, T q) { return MAX ? fmax(p, q) : fmin(p, q); };
-    x = f(x, dpp_move<0xB1>(x));    // quad_perm [1,0,3,2]
-    x = f(x, dpp_move<0x4E>(x));    // quad_perm [2,3,0,1]
-    x = f(x, dpp_move<0x141>(x));   // row_half_mirror: lane i <- lane 7-i of its half row
-    x = f(x, dpp_move<0x140>(x));   // row_mirror: lane i <- lane 15-i of its row
-    return f(f(read_lane(x, 0), read_lane(x, 16)), f(read_lane(x, 32), read_lane(x, 48)));
+    x = f(x, dpp_move<0xB1>(x));        // quad_perm [1,0,3,2]
+    x = f(x, dpp_move<0x4E>(x));        // quad_perm [2,3,0,1]
+    x = f(x, dpp_move<0x141>(x));       // row_half_mirror: lane i <- lane 7-i of its half row
+    x = f(x, dpp_move<0x140>(x));       // row_mirror: lane i <- lane 15-i of its row
+    x = f(x, dpp_move<0x142, 0xA>(x));  // row_bcast:15, rows 1 and 3
+    x = f(x, dpp_move<0x143, 0xC>(x));  // row_bcast:31, rows 2 and 3
+    return read_lane(x, 63);
+}
+// FP32: the fold runs on order-preserving integer keys (x >= +0 keeps its bits, x <= -0
+// has its magnitude bits flipped, so -0 < +0 and the order is total), whose integer
+// min/max need no NaN quieting of the moved values and take each move as an operand.
+__device__ inline int float_key(float x) {
+    const int b = __float_as_int(x);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ inline float key_float(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+// A lane the move does not write keeps the fold's identity, so the compiler can fuse the
+// move into the min/max.
+template <bool MAX, int CTRL, int ROWS = 0xF>
+__device__ inline int fold_step(int k) {
+    constexpr int kIdentity = MAX ? INT_MIN : INT_MAX;
+    const int m = __builtin_amdgcn_update_dpp(kIdentity, k, CTRL, ROWS, 0xF, false);
+    return MAX ? max(k, m) : min(k, m);
+}
+template <bool MAX>
+__device__ inline float wave_fold(float x) {
+    int k = float_key(x);
+    k = fold_step<MAX, 0xB1>(k);
+    k = fold_step<MAX, 0x4E>(k);
+    k = fold_step<MAX, 0x141>(k);
+    k = fold_step<MAX, 0x140>(k);
+    k = fold_step<MAX, 0x142, 0xA>(k);
+    k = fold_step<MAX, 0x143, 0xC>(k);
+    return key_float(__builtin_amdgcn_readlane(k, 63));
 }
 template <typename T>
 __device__ inline T wave_min(T x) { return wave_fold<false>(x); }

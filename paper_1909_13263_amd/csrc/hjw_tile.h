@@ -137,6 +137,22 @@ __host__ inline bool any_lane(bool p) { return p; }
 // arithmetic built on it, in scalar registers.
 __device__ inline int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __host__ inline int uniform_int(int x) { return x; }
+// Product of two values below 2^24 (grid sides are at most 2^20): one full-rate multiply.
+__device__ inline uint32_t mul_u24(uint32_t x, uint32_t y) { return __umul24(x, y); }
+__host__ inline uint32_t mul_u24(uint32_t x, uint32_t y) { return x * y; }
+// Element `off` of an array that starts at `base`, the offset taken in bytes as a 32-bit
+// unsigned value: with a base that is uniform over the wave, the load or store addresses
+// it as a scalar base plus a 32-bit vector offset, with no 64-bit arithmetic per element.
+// Callers keep off * sizeof(X) below 2^32 (offsets inside a tile's rows of one grid).
+template <typename X>
+__host__ __device__ inline const X& at(const X* base, uint32_t off) {
+    return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) +
+                                       off * uint32_t(sizeof(X)));
+}
+template <typename X>
+__host__ __device__ inline X& at(X* base, uint32_t off) {
+    return *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + off * uint32_t(sizeof(X)));
+}
 // Products that are rounded on their own (never fused into an add), so that sums
 // like a*u + b*v are symmetric under exchanging (a,u) and (b,v) bit for bit.
 // (The pragma takes the product out of FMA contraction; __fmul_rn does not.)
@@ -151,7 +167,7 @@ __host__ __device__ inline double mul_rn(double a, double b) {
 
 template <typename T>
 __host__ __device__ inline bool finite_t(T x) {
-    return x - x == T(0);  // false for inf and NaN
+    return __builtin_isfinite(x);  // one class test on the device
 }
 
 // Relative half-gap below which M comes from the midpoint series, and the
@@ -543,11 +559,26 @@ __host__ __device__ inline P node_value(const StageArgs<T, P>& a, int64_t idx, d
     }
 }
 
+// The same, for the node `off` elements after the node `base` (a tile's uniform origin).
+template <int STAGE, typename T, typename P>
+__host__ __device__ inline P node_value_at(const StageArgs<T, P>& a, int64_t base, uint32_t off,
+                                           double dt, double ax, double ay) {
+    if (STAGE == kStageMid) {
+        const Flux3<T> f = at(reinterpret_cast<const Flux3<T>*>(a.flux) + base, off);
+        const double r = double(f.h) - (mul_rn(ax, double(f.dx)) + mul_rn(ay, double(f.dy)));
+        return P(fma(-dt, r, double(at(a.phi_n + base, off))));
+    } else if (STAGE == kStageLast) {
+        return at(a.phi_s + base, off);
+    } else {
+        return at(a.phi_n + base, off);
+    }
+}
+
 // Wrap or extrapolate one index; returns the real index and, for an
 // extrapolated ghost g = 1..3 beyond the edge, g (0 otherwise).  Indices far
 // outside (only in the unused part of a partial tile) are clamped.
-__host__ __device__ inline int64_t resolve(int64_t i, int64_t n, int bc, int& ghost,
-                                           int& side) {
+// Coordinates are 32-bit: a side has at most 2^30 nodes.
+__host__ __device__ inline int resolve(int i, int n, int bc, int& ghost, int& side) {
     ghost = 0;
     side = 0;
     if (i >= 0 && i < n) return i;
@@ -555,7 +586,7 @@ __host__ __device__ inline int64_t resolve(int64_t i, int64_t n, int bc, int& gh
         // one wrap reaches every node a real node's stencil needs (they lie within 3 of
         // the grid, and n >= 8); nodes further out belong to the unused part of a partial
         // tile and are clamped
-        const int64_t r = i < 0 ? i + n : i - n;
+        const int r = i < 0 ? i + n : i - n;
         return r < 0 ? 0 : (r >= n ? n - 1 : r);
     }
     if (i < 0) {
@@ -564,10 +595,16 @@ __host__ __device__ inline int64_t resolve(int64_t i, int64_t n, int bc, int& gh
         if (ghost > 3) ghost = 3;
         return 0;
     }
-    ghost = int(i - n + 1);
+    ghost = i - n + 1;
     side = 1;
     if (ghost > 3) ghost = 3;
     return n - 1;
+}
+
+// Index of node (i, j) of a grid nx wide (0 <= i, j < 2^31, nx < 2^32): one 32 x 32-bit
+// multiply-add into 64 bits.
+__host__ __device__ inline int64_t grid_index(int j, int i, int64_t nx) {
+    return int64_t(uint64_t(uint32_t(j)) * uint64_t(uint32_t(nx)) + uint64_t(uint32_t(i)));
 }
 
 // Where the stage input at (i, j) comes from, ghosts included: idx0 is the node (the
@@ -580,11 +617,11 @@ template <typename T, typename P>
 __host__ __device__ inline void ghost_pair(const StageArgs<T, P>& a, int64_t i, int64_t j,
                                            int64_t& idx0, int64_t& idx1, int& g) {
     int gx, sx, gy, sy;
-    const int64_t ri = resolve(i, a.nx, a.bcx, gx, sx);
-    const int64_t rj = resolve(j, a.ny, a.bcy, gy, sy);
+    const int ri = resolve(int(i), int(a.nx), a.bcx, gx, sx);
+    const int rj = resolve(int(j), int(a.ny), a.bcy, gy, sy);
     const bool ex = gx > 0 && gy == 0, ey = gy > 0 && gx == 0;
-    idx0 = rj * a.nx + ri;
-    idx1 = (ey ? rj - sy : rj) * a.nx + (ex ? ri - sx : ri);
+    idx0 = grid_index(rj, ri, a.nx);
+    idx1 = grid_index(ey ? rj - sy : rj, ex ? ri - sx : ri, a.nx);
     g = ex ? gx : (ey ? gy : 0);
 }
 
@@ -645,14 +682,16 @@ struct Tile {
         P val[kPerThread];
         P cen[kPerThread];
         if (inside(a, x0, y0)) {
-            const int64_t base = (y0 - 3) * a.nx + (x0 - 3);   // global index of phiL[0]
+            // global index of phiL[0], uniform; an element's offset from it is below
+            // (TY + 6) nx + TX + 6 elements, which fits 32 bits in bytes
+            const int64_t base = (y0 - 3) * a.nx + (x0 - 3);
 #pragma unroll
             for (int j = 0; j < kPerThread; ++j) {
                 int r, c;
                 plus_node(element(j), r, c);
-                const int64_t idx = base + r * a.nx + c;
-                val[j] = node_value<STAGE>(a, idx, dt, ax, ay);
-                if (kCenter && j * kThreads < TY * TX) cen[j] = a.phi_n[idx];
+                const uint32_t off = mul_u24(uint32_t(r), uint32_t(a.nx)) + uint32_t(c);
+                val[j] = node_value_at<STAGE>(a, base, off, dt, ax, ay);
+                if (kCenter && j * kThreads < TY * TX) cen[j] = at(a.phi_n + base, off);
             }
         } else if (a.bcx == kBcPeriodic && a.bcy == kBcPeriodic) {
             // every halo index wraps to one node: one value per element
@@ -675,9 +714,10 @@ struct Tile {
                 val[j] = node_value<STAGE>(a, i0[j], dt, ax, ay);
                 if (kCenter && j * kThreads < TY * TX) {
                     const int e = element(j);
-                    const int64_t i = x0 + (e % TX), jj = y0 + (e / TX);
-                    const int64_t ic = i < a.nx ? i : a.nx - 1, jc = jj < a.ny ? jj : a.ny - 1;
-                    cen[j] = a.phi_n[jc * a.nx + ic];
+                    const int i = int(x0) + (e % TX), jj = int(y0) + (e / TX);
+                    const int ic = i < a.nx ? i : int(a.nx) - 1;
+                    const int jc = jj < a.ny ? jj : int(a.ny) - 1;
+                    cen[j] = a.phi_n[grid_index(int(jc), int(ic), a.nx)];
                 }
             }
         } else {
@@ -703,9 +743,10 @@ struct Tile {
                 if (kCenter && j * kThreads < TY * TX) {
                     // the tile's own node, clamped into the grid on a partial tile
                     const int e = element(j);
-                    const int64_t i = x0 + (e % TX), jj = y0 + (e / TX);
-                    const int64_t ic = i < a.nx ? i : a.nx - 1, jc = jj < a.ny ? jj : a.ny - 1;
-                    cen[j] = a.phi_n[jc * a.nx + ic];
+                    const int i = int(x0) + (e % TX), jj = int(y0) + (e / TX);
+                    const int ic = i < a.nx ? i : int(a.nx) - 1;
+                    const int jc = jj < a.ny ? jj : int(a.ny) - 1;
+                    cen[j] = a.phi_n[grid_index(int(jc), int(ic), a.nx)];
                 }
             }
         }
@@ -769,10 +810,17 @@ struct Tile {
     }
     __host__ __device__ static int64_t own_index(int e, const StageArgs<T, P>& a, int64_t x0,
                                                  int64_t y0) {
-        return (y0 + e / TX) * a.nx + (x0 + e % TX);
+        return grid_index(int(y0) + e / TX, int(x0) + e % TX, a.nx);
     }
+    // Tiles whose halo lies inside the grid; their loads take each element's offset from
+    // the tile's origin in 32 bits (load(), gather()), which rows of at most kOffsetNx
+    // nodes allow: (TY + 6) rows of 24-byte flux records stay below 2^32 bytes, and the
+    // row multiply below 2^24.  Tiles of wider grids take the general path.
+    static constexpr int64_t kOffsetNx = int64_t(1) << 22;
+    static_assert((TY + 6) * kOffsetNx * 24 < (int64_t(1) << 32), "32-bit tile offsets");
     __host__ __device__ static bool inside(const StageArgs<T, P>& a, int64_t x0, int64_t y0) {
-        return x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx && y0 + TY + 3 <= a.ny;
+        return a.nx <= kOffsetNx && x0 >= 3 && y0 >= 3 && x0 + TX + 3 <= a.nx &&
+               y0 + TY + 3 <= a.ny;
     }
     // Loads only, into registers (the idle threads of the last round load a valid
     // element): nothing here waits for them, so the step plan's loads, issued before,
@@ -789,10 +837,15 @@ struct Tile {
             const int e = tid + j * kThreads;
             int r, c;
             plus_node(e < kPlusElems ? e : kPlusElems - 1, r, c);
-            int64_t idx;
             if (!EDGE) {
-                idx = base + r * a.nx + c;
-            } else if (own_round(j) && full) {
+                // a uniform base and 32-bit offsets, as in load()
+                const uint32_t off = mul_u24(uint32_t(r), uint32_t(a.nx)) + uint32_t(c);
+                g.pn[j] = at(a.phi_n + base, off);
+                g.f[j] = at(reinterpret_cast<const Flux3<T>*>(a.flux) + base, off);
+                continue;
+            }
+            int64_t idx;
+            if (own_round(j) && full) {
                 idx = own_index(e, a, x0, y0);
             } else {
                 int64_t i1;
@@ -961,6 +1014,7 @@ struct Finisher {
     static constexpr bool kTimed = TIMED;
     const StageArgs<T, P>& a;
     int64_t x0, y0;
+    int room_x;                 // nodes of the grid from x0 on (capped): col < room_x is inside
     double dt, ax, ay;
     T axT, ayT;                 // the dissipation in the stencil precision
     T lo_u, hi_u, lo_v, hi_v;
@@ -972,7 +1026,9 @@ struct Finisher {
 
     __host__ __device__ Finisher(const StageArgs<T, P>& args, int64_t x0_, int64_t y0_,
                                  double dt_, double ax_, double ay_, int dim_)
-        : a(args), x0(x0_), y0(y0_), dt(dt_), ax(ax_), ay(ay_), axT(T(ax_)), ayT(T(ay_)),
+        : a(args), x0(x0_), y0(y0_),
+          room_x(int(args.nx - x0_ < int64_t(1) << 30 ? args.nx - x0_ : int64_t(1) << 30)),
+          dt(dt_), ax(ax_), ay(ay_), axT(T(ax_)), ayT(T(ay_)),
           lo_u(T(INFINITY)),
           hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {
         if (TIMED && STAGE != kStageDeriv && a.ham == kHTimed) {
@@ -1042,9 +1098,13 @@ struct Finisher {
     __host__ __device__ void node(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
         constexpr bool EXT = MODE != kNodePlain;   // held layers can occur
         const int64_t i = x0 + col, j = y0 + row;
-        if (i >= a.nx || j >= a.ny) return;
-        const int64_t idx = j * a.nx + i;
+        if (col >= room_x || j >= a.ny) return;
+        // the node's row in this tile starts at rbase, uniform over a wave where the row is;
+        // stores address it plus the 32-bit column
+        const int64_t rbase = j * a.nx + x0;
+        const uint32_t ucol = uint32_t(col);
         if (STAGE == kStageDeriv) {
+            const int64_t idx = rbase + col;
             a.dout0[idx] = double(um);
             a.dout1[idx] = double(up);
             if (dim == 2) {
@@ -1056,7 +1116,7 @@ struct Finisher {
         const bool hold = EXT && held(i, j);
         if (STAGE == kStagePre && hold) {
             // phi_1 = phi^n - dt (0 - 0) is phi^n exactly
-            reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{T(0), T(0), T(0)};
+            at(reinterpret_cast<Flux3<T>*>(a.flux) + rbase, ucol) = Flux3<T>{T(0), T(0), T(0)};
             return;
         }
         const T ub = T(0.5) * (up + um), vb = T(0.5) * (vp + vm);
@@ -1085,9 +1145,9 @@ struct Finisher {
             // alpha is known here: the record holds the whole numerical Hamiltonian (the
             // second stage subtracts the global alpha times zero)
             const double r = double(H) - (mul_rn(lax, double(Dx)) + mul_rn(lay, double(Dy)));
-            reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{T(r), T(0), T(0)};
+            at(reinterpret_cast<Flux3<T>*>(a.flux) + rbase, ucol) = Flux3<T>{T(r), T(0), T(0)};
         } else if (STAGE == kStagePre) {
-            reinterpret_cast<Flux3<T>*>(a.flux)[idx] = Flux3<T>{H, Dx, Dy};
+            at(reinterpret_cast<Flux3<T>*>(a.flux) + rbase, ucol) = Flux3<T>{H, Dx, Dy};
         }
         if (STAGE == kStagePre) {
             lo_u = fmin(lo_u, fmin(um, up));
@@ -1112,7 +1172,7 @@ struct Finisher {
             res = fma(1.0 / 3.0, pn, mul_rn(2.0 / 3.0, euler));
         }
         const P outv = EXT && hold ? pn_ : P(res);
-        a.out[idx] = outv;
+        at(a.out + rbase, ucol) = outv;
         if (!finite_t(outv)) bad = true;
     }
 };
