@@ -21,6 +21,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "hjw_common.h"
 #include "hjw_tile.h"
@@ -229,10 +230,19 @@ __device__ inline bool plan_finish(const StageArgs<T, P>& a, int bid, const Plan
         // an empty fence: the test of b below cannot be moved up to the load of b (it
         // would wait there for the loads a caller issues between plan_issue and here)
         asm volatile("" : "+v"(b));
-        r0 = wave_min(r0);
-        r1 = wave_max(r1);
-        r2 = wave_min(r2);
-        r3 = wave_max(r3);
+        // an FP32 stencil's ranges are FP32 values (widened exactly): they fold as FP32
+        // keys; NaNs of empty slots sort past every value, as fmin/fmax ignore them
+        if (std::is_same<T, float>::value) {
+            r0 = double(wave_min(float(r0)));
+            r1 = double(wave_max(float(r1)));
+            r2 = double(wave_min(float(r2)));
+            r3 = double(wave_max(float(r3)));
+        } else {
+            r0 = wave_min(r0);
+            r1 = wave_max(r1);
+            r2 = wave_min(r2);
+            r3 = wave_max(r3);
+        }
         b = __any(b != 0u) ? 1u : 0u;
         if (threadIdx.x == 0) {
             if (step_open(s)) {

@@ -962,7 +962,7 @@ struct Tile {
             const T p = col_half ? vp[j] : vL[kVElems / 2 + slot];
             fin.template node<MODE>(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col],
                                    m, p, phiL[(row + 3) * PW + col + 3],
-                                   pnL ? pnL[row * TX + col] : P(0));
+                                   Fin::kUsesPn ? pnL[row * TX + col] : P(0));
         }
     }
 };
@@ -1012,9 +1012,13 @@ struct Tile1D {
 template <int STAGE, typename T, typename P, bool TIMED>
 struct Finisher {
     static constexpr bool kTimed = TIMED;
+    // the second and third stages read phi^n at the node (a compile-time fact: an LDS
+    // array's address may be 0, so a test of the pointer would stay in the code)
+    static constexpr bool kUsesPn = STAGE == kStageMid || STAGE == kStageLast;
     const StageArgs<T, P>& a;
     int64_t x0, y0;
-    int room_x;                 // nodes of the grid from x0 on (capped): col < room_x is inside
+    int room_x, room_y;         // nodes of the grid from x0 (y0) on, capped: col < room_x
+                                // and row < room_y is inside
     double dt, ax, ay;
     T axT, ayT;                 // the dissipation in the stencil precision
     T lo_u, hi_u, lo_v, hi_v;
@@ -1028,6 +1032,7 @@ struct Finisher {
                                  double dt_, double ax_, double ay_, int dim_)
         : a(args), x0(x0_), y0(y0_),
           room_x(int(args.nx - x0_ < int64_t(1) << 30 ? args.nx - x0_ : int64_t(1) << 30)),
+          room_y(int(args.ny - y0_ < int64_t(1) << 30 ? args.ny - y0_ : int64_t(1) << 30)),
           dt(dt_), ax(ax_), ay(ay_), axT(T(ax_)), ayT(T(ay_)),
           lo_u(T(INFINITY)),
           hi_u(T(-INFINITY)), lo_v(T(INFINITY)), hi_v(T(-INFINITY)), bad(false), dim(dim_) {
@@ -1097,11 +1102,11 @@ struct Finisher {
     template <int MODE>
     __host__ __device__ void node(int col, int row, T um, T up, T vm, T vp, P ps, P pn_) {
         constexpr bool EXT = MODE != kNodePlain;   // held layers can occur
-        const int64_t i = x0 + col, j = y0 + row;
-        if (col >= room_x || j >= a.ny) return;
+        const int i = int(x0) + col, j = int(y0) + row;   // sides are at most 2^30 nodes
+        if (col >= room_x || row >= room_y) return;
         // the node's row in this tile starts at rbase, uniform over a wave where the row is;
         // stores address it plus the 32-bit column
-        const int64_t rbase = j * a.nx + x0;
+        const int64_t rbase = int64_t(j) * a.nx + x0;
         const uint32_t ucol = uint32_t(col);
         if (STAGE == kStageDeriv) {
             const int64_t idx = rbase + col;
