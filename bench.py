@@ -67,39 +67,39 @@ def kernel_bytes_per_cell(phi_b, flux_b):
 # (SQ_INSTS_VALU_* x 64 / nodes).  Valid only while the kernel sources hash to the recorded
 # SHA-256; after any change the counter-derived fields are null until re-measured.
 MEASURED = {
-    "source_sha256": "5fb88eb151e939bc24ee999d92fa06ccaa5dedfb73ddc6ccc6331cb003abe8a3",
+    "source_sha256": "b71d71188dc609065af5d036add9facc33fa3add71e60379de7efccbfd98a683",
     "runs": {
         "fp32_stencil/1024": {
-            "pre": {"fetch_kib": 4584.5, "write_kib": 12416.0, "traffic_bytes": 22103049,
-                    "valu_per_node": {"f32": 181.0, "f64": 6.5, "i32": 20.44, "cvt": 4.75, "i64": 10.9, "trans_f32": 13.25, "trans_f64": 0.0, "other": 72.21}},
-            "mid": {"fetch_kib": 11056.0, "write_kib": 8192.1, "traffic_bytes": 31031500,
-                    "valu_per_node": {"f32": 182.0, "f64": 18.31, "i32": 23.19, "cvt": 9.75, "i64": 12.73, "trans_f32": 13.25, "trans_f64": 0.06, "other": 50.4}},
-            "last": {"fetch_kib": 8675.0, "write_kib": 8194.2, "traffic_bytes": 26157312,
-                    "valu_per_node": {"f32": 182.0, "f64": 10.5, "i32": 25.78, "cvt": 5.25, "i64": 11.05, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.98}},
+            "pre": {"fetch_kib": 4571.3, "write_kib": 12416.0, "traffic_bytes": 22075928,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 30.8, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 41.11}},
+            "mid": {"fetch_kib": 11038.5, "write_kib": 8192.1, "traffic_bytes": 30995660,
+                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 26.7, "cvt": 10.25, "i64": 4.5, "trans_f32": 13.25, "trans_f64": 0.06, "other": 33.86}},
+            "last": {"fetch_kib": 8666.0, "write_kib": 8194.2, "traffic_bytes": 26138880,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 26.11, "cvt": 5.25, "i64": 2.55, "trans_f32": 13.25, "trans_f64": 0.0, "other": 31.81}},
         },
         "fp32_stencil/2048": {
-            "pre": {"fetch_kib": 17094.9, "write_kib": 49664.0, "traffic_bytes": 85866202,
-                    "valu_per_node": {"f32": 181.0, "f64": 6.5, "i32": 20.26, "cvt": 4.75, "i64": 10.58, "trans_f32": 13.25, "trans_f64": 0.0, "other": 72.07}},
-            "mid": {"fetch_kib": 42249.5, "write_kib": 32768.0, "traffic_bytes": 120081351,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 21.97, "cvt": 9.75, "i64": 11.96, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.51}},
-            "last": {"fetch_kib": 33462.8, "write_kib": 32770.2, "traffic_bytes": 102088614,
-                    "valu_per_node": {"f32": 182.0, "f64": 10.5, "i32": 25.7, "cvt": 5.25, "i64": 10.41, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.28}},
+            "pre": {"fetch_kib": 17075.2, "write_kib": 49664.0, "traffic_bytes": 85825996,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 30.62, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 40.62}},
+            "mid": {"fetch_kib": 42236.5, "write_kib": 32768.0, "traffic_bytes": 120054737,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 23.91, "cvt": 9.75, "i64": 3.6, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.28}},
+            "last": {"fetch_kib": 33452.8, "write_kib": 32770.2, "traffic_bytes": 102068101,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 25.81, "cvt": 5.25, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 31.04}},
         },
         "fp32_stencil/4096": {
-            "pre": {"fetch_kib": 66715.0, "write_kib": 198656.0, "traffic_bytes": 340056102,
-                    "valu_per_node": {"f32": 181.0, "f64": 6.5, "i32": 20.16, "cvt": 4.75, "i64": 10.42, "trans_f32": 13.25, "trans_f64": 0.0, "other": 72.01}},
-            "mid": {"fetch_kib": 166205.3, "write_kib": 131072.0, "traffic_bytes": 474606199,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 21.8, "cvt": 9.75, "i64": 11.86, "trans_f32": 13.25, "trans_f64": 0.0, "other": 35.38}},
-            "last": {"fetch_kib": 132198.4, "write_kib": 131074.2, "traffic_bytes": 404962399,
-                    "valu_per_node": {"f32": 182.0, "f64": 10.5, "i32": 25.66, "cvt": 5.25, "i64": 10.08, "trans_f32": 13.25, "trans_f64": 0.0, "other": 34.92}},
+            "pre": {"fetch_kib": 66686.5, "write_kib": 198656.0, "traffic_bytes": 339997772,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 30.53, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 40.37}},
+            "mid": {"fetch_kib": 166168.2, "write_kib": 131072.0, "traffic_bytes": 474530181,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 23.83, "cvt": 9.75, "i64": 3.42, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.05}},
+            "last": {"fetch_kib": 132188.5, "write_kib": 131074.2, "traffic_bytes": 404941980,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 25.66, "cvt": 5.25, "i64": 1.58, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.65}},
         },
         "fp64/1024": {
-            "pre": {"fetch_kib": 4770.5, "write_kib": 24704.0, "traffic_bytes": 35066956,
-                    "valu_per_node": {"f32": 0.25, "f64": 282.75, "i32": 19.19, "cvt": 0.5, "i64": 10.9, "trans_f32": 0.25, "trans_f64": 10.75, "other": 134.33}},
-            "mid": {"fetch_kib": 17707.1, "write_kib": 8192.1, "traffic_bytes": 44652828,
-                    "valu_per_node": {"f32": 0.25, "f64": 295.56, "i32": 20.97, "cvt": 0.5, "i64": 13.53, "trans_f32": 0.25, "trans_f64": 10.81, "other": 89.79}},
-            "last": {"fetch_kib": 8841.5, "write_kib": 8194.2, "traffic_bytes": 26498313,
-                    "valu_per_node": {"f32": 0.25, "f64": 287.75, "i32": 25.03, "cvt": 0.5, "i64": 11.05, "trans_f32": 0.25, "trans_f64": 10.75, "other": 71.85}},
+            "pre": {"fetch_kib": 4750.0, "write_kib": 24704.0, "traffic_bytes": 35024967,
+                    "valu_per_node": {"f32": 0.25, "f64": 279.75, "i32": 22.55, "cvt": 0.5, "i64": 2.36, "trans_f32": 0.25, "trans_f64": 10.75, "other": 115.73}},
+            "mid": {"fetch_kib": 17691.5, "write_kib": 8192.1, "traffic_bytes": 44620966,
+                    "valu_per_node": {"f32": 0.25, "f64": 295.12, "i32": 24.41, "cvt": 0.5, "i64": 4.34, "trans_f32": 0.25, "trans_f64": 10.81, "other": 77.17}},
+            "last": {"fetch_kib": 8842.5, "write_kib": 8194.2, "traffic_bytes": 26500357,
+                    "valu_per_node": {"f32": 0.25, "f64": 286.75, "i32": 25.86, "cvt": 0.5, "i64": 2.55, "trans_f32": 0.25, "trans_f64": 10.75, "other": 67.44}},
         },
     },
 }
