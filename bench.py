@@ -176,6 +176,11 @@ def parse():
                     help="arrival rate as a fraction of the measured saturation rate")
     ap.add_argument("--serve-pool-gib", type=float, default=4.0)
     ap.add_argument("--serve-max-active", type=int, default=256)
+    ap.add_argument("--serve-sustain-sample", type=int, default=768,
+                    help="requests replayed closed-loop to measure the sustained throughput")
+    ap.add_argument("--serve-outstanding", type=int, default=0,
+                    help="requests kept in the server during the closed-loop replay "
+                         "(0: --serve-max-active, the server kept full)")
     ap.add_argument("--serve-sat-sample", type=int, default=256,
                     help="requests submitted at once to measure the saturation rate")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -476,6 +481,11 @@ def served_stream(args, hjw):
     S.saturation(srv, reqs[:16], phi0s[:16])
     k = min(args.serve_sat_sample, len(reqs))
     sat_rps, sat_cells, sat_wall = S.saturation(srv, reqs[-k:], phi0s[-k:])
+    # the same server kept full (closed loop): the throughput it sustains without the drain
+    sus_rps, sus_cells, sus_wall, sus_n = S.sustained(srv, reqs[:args.serve_sustain_sample],
+                                                      phi0s[:args.serve_sustain_sample],
+                                                      outstanding=args.serve_outstanding or
+                                                      args.serve_max_active)
     rate = args.serve_load * sat_rps
     before = srv.stats()
     t1 = time.perf_counter()
@@ -490,6 +500,11 @@ def served_stream(args, hjw):
         "arrival_rate_rps": rate, "load": args.serve_load,
         "saturation_rps": sat_rps, "saturation_cell_updates_per_s": sat_cells,
         "saturation_sample": f"last {k} requests of the stream submitted at once ({sat_wall:.1f} s)",
+        "sustained_rps": sus_rps, "sustained_cell_updates_per_s": sus_cells,
+        "sustained_sample": (f"first {args.serve_sustain_sample} requests of the stream, "
+                             f"{args.serve_outstanding or args.serve_max_active} kept in the "
+                             f"server, {sus_n} timed "
+                             f"after the first 64 finished, drain excluded ({sus_wall:.1f} s)"),
         "p50_ms": summary["p50_ms"], "p90_ms": summary["p90_ms"], "p99_ms": summary["p99_ms"],
         "max_ms": summary["max_ms"], "mean_ms": summary["mean_ms"],
         "cell_updates_per_s": summary["cell_updates"] / wall,

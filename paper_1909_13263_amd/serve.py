@@ -84,6 +84,40 @@ def saturation(server: hjw.Server, requests, phi0s, chunks=4):
     return len(requests) / wall, stages / wall, wall
 
 
+def sustained(server: hjw.Server, requests, phi0s, outstanding=128, warm=64, chunks=1):
+    """Closed-loop throughput with the server kept full: `outstanding` requests are in the
+    server at all times (a new one is submitted as each finishes, in list order).  Timed
+    from the `warm`-th completion until the list is exhausted, so that neither the ramp
+    nor the final drain (where the last long solves run alone) enters the figure.
+    Returns (requests per second, cell-stages per second, wall seconds, requests timed)."""
+    nxt = 0
+    inflight = 0
+    done = 0
+    t0 = st0 = None
+    done0 = 0
+    while nxt < len(requests):
+        while inflight < outstanding and nxt < len(requests):
+            server.submit(requests[nxt].problem, phi0s[nxt])
+            nxt += 1
+            inflight += 1
+        server.run(chunks)
+        for sid in server.completed():
+            res = server.result(sid)
+            if res.status != hjw.OK:
+                raise RuntimeError("a request failed while measuring sustained throughput")
+            inflight -= 1
+            done += 1
+            if t0 is None and done >= warm:
+                t0, st0, done0 = time.perf_counter(), server.stats()["node_stages"], done
+    if t0 is None:
+        raise ValueError("too few requests to time")
+    wall = time.perf_counter() - t0
+    stages = server.stats()["node_stages"] - st0
+    timed = done - done0
+    server.drain()
+    return timed / wall, stages / wall, wall, timed
+
+
 def summarize(records, wall):
     lat = np.array([r["latency"] for r in records.values()])
     ok = [r for r in records.values() if r["status"] == hjw.OK]

@@ -265,3 +265,25 @@ def test_bursts_larger_than_one_staging_step():
         res = results[k]
         assert res.status == hjw.OK and res.info.steps == info.steps and res.info.t == info.t
         assert np.array_equal(res.phi, ref), (k, np.abs(res.phi - ref).max())
+
+
+def test_sustained_closed_loop_keeps_the_server_full():
+    """The closed-loop throughput driver: a fixed number of requests stays in the server,
+    every request completes with its single-grid result, and the figure is positive."""
+    reqs = _mix(48, seed=91)
+    srv = hjw.Server(MIXED, pool_bytes=128 << 20, max_active=16)
+    seen = []
+    orig_submit = srv.submit
+
+    def submit(problem, phi0=None, scheme=hjw.WENO_L):
+        st = srv.stats()
+        seen.append(st["active"] + st["queued"])
+        return orig_submit(problem, phi0, scheme)
+
+    srv.submit = submit
+    rps, cells, wall, timed = S.sustained(srv, reqs, S.prepare(reqs), outstanding=8, warm=8)
+    st = srv.stats()
+    srv.close()
+    assert rps > 0 and cells > 0 and wall > 0 and 0 < timed <= len(reqs)
+    assert max(seen) <= 8
+    assert st["done"] == len(reqs) and st["failed"] == 0 and st["pool_in_use"] == 0
