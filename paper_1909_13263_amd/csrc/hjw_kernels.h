@@ -339,7 +339,10 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     const int tile = tile_of_block(bid, nb, a.remap);
     const int64_t x0 = int64_t(tile % a.nbx) * kTX;
     const int64_t y0 = int64_t(tile / a.nbx) * TY;
+    // the workgroup is exactly the tile's threads: with the range known, the compiler
+    // resolves at compile time which rounds of the load cover the tile's own nodes
     const int tid = threadIdx.x;
+    __builtin_assume(tid >= 0 && tid < TL::kThreads);
     double dt, ax, ay;
     const bool interior = TL::inside(a, x0, y0);
     // periodic edge tiles take the same path on the FP32 stencil; on FP64 the second
@@ -405,6 +408,7 @@ __global__ __launch_bounds__(256) void k_stage1d(StageArgs<T, P> a) {
     if (!stage_entry<STAGE>(a, int(blockIdx.x), dt, ax, ay)) return;
     const int64_t x0 = int64_t(blockIdx.x) * kTX1;
     const int tid = threadIdx.x;
+    __builtin_assume(tid >= 0 && tid < 256);
     TL::template load<STAGE>(tid, a, x0, dt, ax, 0.0, phiL, pnL);
     __syncthreads();
     TL::sweep_x(tid, a, phiL, uL);
