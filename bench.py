@@ -67,39 +67,39 @@ def kernel_bytes_per_cell(phi_b, flux_b):
 # (SQ_INSTS_VALU_* x 64 / nodes).  Valid only while the kernel sources hash to the recorded
 # SHA-256; after any change the counter-derived fields are null until re-measured.
 MEASURED = {
-    "source_sha256": "b71d71188dc609065af5d036add9facc33fa3add71e60379de7efccbfd98a683",
+    "source_sha256": "97f2bdd09d94e9ad26584aa949213f80654bebf442f424874c0a1638debc18ea",
     "runs": {
         "fp32_stencil/1024": {
-            "pre": {"fetch_kib": 4571.3, "write_kib": 12416.0, "traffic_bytes": 22075928,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 30.8, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 41.11}},
-            "mid": {"fetch_kib": 11038.5, "write_kib": 8192.1, "traffic_bytes": 30995660,
-                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 26.7, "cvt": 10.25, "i64": 4.5, "trans_f32": 13.25, "trans_f64": 0.06, "other": 33.86}},
-            "last": {"fetch_kib": 8666.0, "write_kib": 8194.2, "traffic_bytes": 26138880,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 26.11, "cvt": 5.25, "i64": 2.55, "trans_f32": 13.25, "trans_f64": 0.0, "other": 31.81}},
+            "pre": {"fetch_kib": 4563.8, "write_kib": 12416.0, "traffic_bytes": 22060686,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 24.58, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 39.69}},
+            "mid": {"fetch_kib": 11025.5, "write_kib": 8192.1, "traffic_bytes": 30969036,
+                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 21.38, "cvt": 10.25, "i64": 3.86, "trans_f32": 13.25, "trans_f64": 0.06, "other": 34.28}},
+            "last": {"fetch_kib": 8652.5, "write_kib": 8194.2, "traffic_bytes": 26111232,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 18.96, "cvt": 5.25, "i64": 2.39, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.67}},
         },
         "fp32_stencil/2048": {
-            "pre": {"fetch_kib": 17075.2, "write_kib": 49664.0, "traffic_bytes": 85825996,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 30.62, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 40.62}},
-            "mid": {"fetch_kib": 42236.5, "write_kib": 32768.0, "traffic_bytes": 120054737,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 23.91, "cvt": 9.75, "i64": 3.6, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.28}},
-            "last": {"fetch_kib": 33452.8, "write_kib": 32770.2, "traffic_bytes": 102068101,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 25.81, "cvt": 5.25, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 31.04}},
+            "pre": {"fetch_kib": 17065.9, "write_kib": 49664.0, "traffic_bytes": 85806962,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 24.27, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 39.26}},
+            "mid": {"fetch_kib": 42213.0, "write_kib": 32768.0, "traffic_bytes": 120006680,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 18.75, "cvt": 9.75, "i64": 2.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.77}},
+            "last": {"fetch_kib": 33438.1, "write_kib": 32770.2, "traffic_bytes": 102037931,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 18.55, "cvt": 5.25, "i64": 1.83, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.03}},
         },
         "fp32_stencil/4096": {
-            "pre": {"fetch_kib": 66686.5, "write_kib": 198656.0, "traffic_bytes": 339997772,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 30.53, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 40.37}},
-            "mid": {"fetch_kib": 166168.2, "write_kib": 131072.0, "traffic_bytes": 474530181,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 23.83, "cvt": 9.75, "i64": 3.42, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.05}},
-            "last": {"fetch_kib": 132188.5, "write_kib": 131074.2, "traffic_bytes": 404941980,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 25.66, "cvt": 5.25, "i64": 1.58, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.65}},
+            "pre": {"fetch_kib": 66674.6, "write_kib": 198656.0, "traffic_bytes": 339973305,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 24.1, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 39.04}},
+            "mid": {"fetch_kib": 166148.0, "write_kib": 131072.0, "traffic_bytes": 474488913,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 18.75, "cvt": 9.75, "i64": 2.7, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.57}},
+            "last": {"fetch_kib": 132157.2, "write_kib": 131074.2, "traffic_bytes": 404877980,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 18.34, "cvt": 5.25, "i64": 1.54, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.7}},
         },
         "fp64/1024": {
-            "pre": {"fetch_kib": 4750.0, "write_kib": 24704.0, "traffic_bytes": 35024967,
-                    "valu_per_node": {"f32": 0.25, "f64": 279.75, "i32": 22.55, "cvt": 0.5, "i64": 2.36, "trans_f32": 0.25, "trans_f64": 10.75, "other": 115.73}},
-            "mid": {"fetch_kib": 17691.5, "write_kib": 8192.1, "traffic_bytes": 44620966,
-                    "valu_per_node": {"f32": 0.25, "f64": 295.12, "i32": 24.41, "cvt": 0.5, "i64": 4.34, "trans_f32": 0.25, "trans_f64": 10.81, "other": 77.17}},
-            "last": {"fetch_kib": 8842.5, "write_kib": 8194.2, "traffic_bytes": 26500357,
-                    "valu_per_node": {"f32": 0.25, "f64": 286.75, "i32": 25.86, "cvt": 0.5, "i64": 2.55, "trans_f32": 0.25, "trans_f64": 10.75, "other": 67.44}},
+            "pre": {"fetch_kib": 4739.5, "write_kib": 24704.0, "traffic_bytes": 35003468,
+                    "valu_per_node": {"f32": 0.25, "f64": 279.75, "i32": 16.08, "cvt": 0.5, "i64": 2.36, "trans_f32": 0.25, "trans_f64": 10.75, "other": 114.56}},
+            "mid": {"fetch_kib": 17672.7, "write_kib": 8192.1, "traffic_bytes": 44582490,
+                    "valu_per_node": {"f32": 0.25, "f64": 295.12, "i32": 19.6, "cvt": 0.5, "i64": 3.55, "trans_f32": 0.25, "trans_f64": 10.81, "other": 76.53}},
+            "last": {"fetch_kib": 8818.0, "write_kib": 8194.2, "traffic_bytes": 26450181,
+                    "valu_per_node": {"f32": 0.25, "f64": 286.75, "i32": 18.46, "cvt": 0.5, "i64": 2.39, "trans_f32": 0.25, "trans_f64": 10.75, "other": 66.55}},
         },
     },
 }
@@ -482,10 +482,11 @@ def served_stream(args, hjw):
     k = min(args.serve_sat_sample, len(reqs))
     sat_rps, sat_cells, sat_wall = S.saturation(srv, reqs[-k:], phi0s[-k:])
     # the same server kept full (closed loop): the throughput it sustains without the drain
-    sus_rps, sus_cells, sus_wall, sus_n = S.sustained(srv, reqs[:args.serve_sustain_sample],
-                                                      phi0s[:args.serve_sustain_sample],
-                                                      outstanding=args.serve_outstanding or
-                                                      args.serve_max_active)
+    sus_k = min(args.serve_sustain_sample, len(reqs))
+    sus_out = min(args.serve_outstanding or args.serve_max_active, sus_k // 3)
+    sus_rps, sus_cells, sus_wall, sus_n = S.sustained(srv, reqs[:sus_k], phi0s[:sus_k],
+                                                      outstanding=sus_out,
+                                                      warm=min(64, max(1, sus_out // 2)))
     rate = args.serve_load * sat_rps
     before = srv.stats()
     t1 = time.perf_counter()
@@ -501,10 +502,10 @@ def served_stream(args, hjw):
         "saturation_rps": sat_rps, "saturation_cell_updates_per_s": sat_cells,
         "saturation_sample": f"last {k} requests of the stream submitted at once ({sat_wall:.1f} s)",
         "sustained_rps": sus_rps, "sustained_cell_updates_per_s": sus_cells,
-        "sustained_sample": (f"first {args.serve_sustain_sample} requests of the stream, "
-                             f"{args.serve_outstanding or args.serve_max_active} kept in the "
-                             f"server, {sus_n} timed "
-                             f"after the first 64 finished, drain excluded ({sus_wall:.1f} s)"),
+        "sustained_sample": (f"first {sus_k} requests of the stream, {sus_out} kept in the "
+                             f"server, {sus_n} timed after the first "
+                             f"{min(64, max(1, sus_out // 2))} finished, drain excluded "
+                             f"({sus_wall:.1f} s)"),
         "p50_ms": summary["p50_ms"], "p90_ms": summary["p90_ms"], "p99_ms": summary["p99_ms"],
         "max_ms": summary["max_ms"], "mean_ms": summary["mean_ms"],
         "cell_updates_per_s": summary["cell_updates"] / wall,

@@ -90,6 +90,9 @@ def sustained(server: hjw.Server, requests, phi0s, outstanding=128, warm=64, chu
     from the `warm`-th completion until the list is exhausted, so that neither the ramp
     nor the final drain (where the last long solves run alone) enters the figure.
     Returns (requests per second, cell-stages per second, wall seconds, requests timed)."""
+    if not 0 < warm < len(requests) - outstanding:
+        raise ValueError(f"sustained: need 0 < warm < len(requests) - outstanding "
+                         f"({warm}, {len(requests)}, {outstanding})")
     nxt = 0
     inflight = 0
     done = 0
