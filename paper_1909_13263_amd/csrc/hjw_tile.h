@@ -916,11 +916,11 @@ struct Tile {
     __host__ __device__ static void stash(int t, const T* vm, const T* vp, T* vL) {
         const int col = t % TX;
         const int seg = t / TX;
+        T* v0 = vL + seg * kKeep * TX + col;
 #pragma unroll
         for (int k = kKeep; k < SY; ++k) {
-            const int slot = (seg * kKeep + (k - kKeep)) * TX + col;
-            vL[slot] = vm[k];
-            vL[kVElems / 2 + slot] = vp[k];
+            v0[(k - kKeep) * TX] = vm[k];
+            v0[kVElems / 2 + (k - kKeep) * TX] = vp[k];
         }
     }
 
@@ -954,15 +954,19 @@ struct Tile {
         const int col = t % TX;
         const int seg = uniform_int(t / TX);
         const int first = uniform_int(col_half ? 0 : kKeep);
+        // the thread's LDS entries of its first node; the others lie a fixed stride further
+        // (immediate offsets of the LDS reads, no address arithmetic per node)
+        const int row0 = seg * SY + first;
+        const T* u0 = uL + row0 * UW + col;
+        const T* v0 = vL + seg * kKeep * TX + col;
+        const P* s0 = phiL + (row0 + 3) * PW + col + 3;
+        const P* n0 = Fin::kUsesPn ? pnL + row0 * TX + col : pnL;
 #pragma unroll
         for (int j = 0; j < kKeep; ++j) {
-            const int row = seg * SY + first + j;
-            const int slot = (seg * kKeep + j) * TX + col;
-            const T m = col_half ? vm[j] : vL[slot];
-            const T p = col_half ? vp[j] : vL[kVElems / 2 + slot];
-            fin.template node<MODE>(col, row, uL[row * UW + col], uL[TY * UW + row * UW + col],
-                                   m, p, phiL[(row + 3) * PW + col + 3],
-                                   Fin::kUsesPn ? pnL[row * TX + col] : P(0));
+            const T m = first == 0 ? vm[j] : v0[j * TX];   // first is uniform: a scalar test
+            const T p = first == 0 ? vp[j] : v0[kVElems / 2 + j * TX];
+            fin.template node<MODE>(col, row0 + j, u0[j * UW], u0[TY * UW + j * UW], m, p,
+                                   s0[j * PW], Fin::kUsesPn ? n0[j * TX] : P(0));
         }
     }
 };
@@ -1159,7 +1163,7 @@ struct Finisher {
             hi_u = fmax(hi_u, fmax(um, up));
             lo_v = fmin(lo_v, fmin(vm, vp));
             hi_v = fmax(hi_v, fmax(vm, vp));
-            if (!(finite_t(H) && finite_t(Dx) && finite_t(Dy))) bad = true;
+            bad |= !(finite_t(H) && finite_t(Dx) && finite_t(Dy));
             return;
         }
         // L = -(H - (ax Dx + ay Dy)); the sum is symmetric in x and y
@@ -1178,7 +1182,7 @@ struct Finisher {
         }
         const P outv = EXT && hold ? pn_ : P(res);
         at(a.out + rbase, ucol) = outv;
-        if (!finite_t(outv)) bad = true;
+        bad |= !finite_t(outv);
     }
 };
 
