@@ -67,39 +67,39 @@ def kernel_bytes_per_cell(phi_b, flux_b):
 # (SQ_INSTS_VALU_* x 64 / nodes).  Valid only while the kernel sources hash to the recorded
 # SHA-256; after any change the counter-derived fields are null until re-measured.
 MEASURED = {
-    "source_sha256": "97f2bdd09d94e9ad26584aa949213f80654bebf442f424874c0a1638debc18ea",
+    "source_sha256": "f8c4da55030f36ec690cc75582491ea29dc9c007f00fa5dc448bc3dbac1daa44",
     "runs": {
         "fp32_stencil/1024": {
-            "pre": {"fetch_kib": 4563.8, "write_kib": 12416.0, "traffic_bytes": 22060686,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 24.58, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 39.69}},
-            "mid": {"fetch_kib": 11025.5, "write_kib": 8192.1, "traffic_bytes": 30969036,
-                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 21.38, "cvt": 10.25, "i64": 3.86, "trans_f32": 13.25, "trans_f64": 0.06, "other": 34.28}},
-            "last": {"fetch_kib": 8652.5, "write_kib": 8194.2, "traffic_bytes": 26111232,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 18.96, "cvt": 5.25, "i64": 2.39, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.67}},
+            "pre": {"fetch_kib": 4559.7, "write_kib": 12416.0, "traffic_bytes": 22052324,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 22.71, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.81}},
+            "mid": {"fetch_kib": 11018.0, "write_kib": 8192.1, "traffic_bytes": 30953676,
+                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 17.75, "cvt": 10.25, "i64": 3.86, "trans_f32": 13.25, "trans_f64": 0.06, "other": 33.66}},
+            "last": {"fetch_kib": 8639.0, "write_kib": 8194.2, "traffic_bytes": 26083584,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 15.34, "cvt": 5.25, "i64": 2.39, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.55}},
         },
         "fp32_stencil/2048": {
-            "pre": {"fetch_kib": 17065.9, "write_kib": 49664.0, "traffic_bytes": 85806962,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 24.27, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 39.26}},
-            "mid": {"fetch_kib": 42213.0, "write_kib": 32768.0, "traffic_bytes": 120006680,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 18.75, "cvt": 9.75, "i64": 2.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.77}},
-            "last": {"fetch_kib": 33438.1, "write_kib": 32770.2, "traffic_bytes": 102037931,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 18.55, "cvt": 5.25, "i64": 1.83, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.03}},
+            "pre": {"fetch_kib": 17063.1, "write_kib": 49664.0, "traffic_bytes": 85801064,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 22.39, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.38}},
+            "mid": {"fetch_kib": 42210.5, "write_kib": 32768.0, "traffic_bytes": 120001479,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 15.13, "cvt": 9.75, "i64": 2.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.15}},
+            "last": {"fetch_kib": 33423.5, "write_kib": 32770.2, "traffic_bytes": 102007993,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 14.92, "cvt": 5.25, "i64": 1.83, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.91}},
         },
         "fp32_stencil/4096": {
-            "pre": {"fetch_kib": 66674.6, "write_kib": 198656.0, "traffic_bytes": 339973305,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 24.1, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 39.04}},
-            "mid": {"fetch_kib": 166148.0, "write_kib": 131072.0, "traffic_bytes": 474488913,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 18.75, "cvt": 9.75, "i64": 2.7, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.57}},
-            "last": {"fetch_kib": 132157.2, "write_kib": 131074.2, "traffic_bytes": 404877980,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 18.34, "cvt": 5.25, "i64": 1.54, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.7}},
+            "pre": {"fetch_kib": 66683.7, "write_kib": 198656.0, "traffic_bytes": 339991893,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 22.23, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.16}},
+            "mid": {"fetch_kib": 166147.0, "write_kib": 131072.0, "traffic_bytes": 474486846,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 15.13, "cvt": 9.75, "i64": 2.7, "trans_f32": 13.25, "trans_f64": 0.0, "other": 27.95}},
+            "last": {"fetch_kib": 132150.5, "write_kib": 131074.2, "traffic_bytes": 404864251,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 14.71, "cvt": 5.25, "i64": 1.54, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.58}},
         },
         "fp64/1024": {
-            "pre": {"fetch_kib": 4739.5, "write_kib": 24704.0, "traffic_bytes": 35003468,
-                    "valu_per_node": {"f32": 0.25, "f64": 279.75, "i32": 16.08, "cvt": 0.5, "i64": 2.36, "trans_f32": 0.25, "trans_f64": 10.75, "other": 114.56}},
-            "mid": {"fetch_kib": 17672.7, "write_kib": 8192.1, "traffic_bytes": 44582490,
-                    "valu_per_node": {"f32": 0.25, "f64": 295.12, "i32": 19.6, "cvt": 0.5, "i64": 3.55, "trans_f32": 0.25, "trans_f64": 10.81, "other": 76.53}},
-            "last": {"fetch_kib": 8818.0, "write_kib": 8194.2, "traffic_bytes": 26450181,
-                    "valu_per_node": {"f32": 0.25, "f64": 286.75, "i32": 18.46, "cvt": 0.5, "i64": 2.39, "trans_f32": 0.25, "trans_f64": 10.75, "other": 66.55}},
+            "pre": {"fetch_kib": 4732.5, "write_kib": 24704.0, "traffic_bytes": 34989118,
+                    "valu_per_node": {"f32": 0.25, "f64": 279.75, "i32": 15.21, "cvt": 0.5, "i64": 2.36, "trans_f32": 0.25, "trans_f64": 10.75, "other": 113.69}},
+            "mid": {"fetch_kib": 17681.6, "write_kib": 8192.1, "traffic_bytes": 44600690,
+                    "valu_per_node": {"f32": 0.25, "f64": 295.12, "i32": 15.97, "cvt": 0.5, "i64": 3.55, "trans_f32": 0.25, "trans_f64": 10.81, "other": 76.15}},
+            "last": {"fetch_kib": 8829.5, "write_kib": 8194.2, "traffic_bytes": 26473737,
+                    "valu_per_node": {"f32": 0.25, "f64": 286.75, "i32": 14.84, "cvt": 0.5, "i64": 2.39, "trans_f32": 0.25, "trans_f64": 10.75, "other": 66.67}},
         },
     },
 }
