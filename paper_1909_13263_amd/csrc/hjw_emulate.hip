@@ -163,10 +163,8 @@ struct Emu {
             std::vector<T> vm(size_t(TL::kHalf) * S), vp(size_t(TL::kHalf) * S);
             std::vector<T> vL(TL::kVElems, T(NAN));
             for (int t = 0; t < TL::kHalf; ++t) TL::sweep_x(t, a, phiL.data(), uL.data());
-            for (int t = 0; t < TL::kHalf; ++t) {
-                TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * S], &vp[size_t(t) * S]);
-                TL::stash(t, &vm[size_t(t) * S], &vp[size_t(t) * S], vL.data());
-            }
+            for (int t = 0; t < TL::kHalf; ++t)
+                TL::sweep_y(t, a, phiL.data(), &vm[size_t(t) * S], &vp[size_t(t) * S], vL.data());
             double lu = INFINITY, hu = -INFINITY, lv = INFINITY, hv = -INFINITY;
             bool bad = false;
             for (int t = 0; t < TL::kThreads; ++t) {

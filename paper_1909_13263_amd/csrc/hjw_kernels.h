@@ -374,8 +374,7 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
     if (rows) {
         TL::sweep_x(tid, a, phiL, uL);
     } else {
-        TL::sweep_y(tid - TL::kHalf, a, phiL, vm, vp);
-        TL::stash(tid - TL::kHalf, vm, vp, vL);
+        TL::sweep_y(tid - TL::kHalf, a, phiL, vm, vp, vL);
     }
     __syncthreads();
     Finisher<STAGE, T, P, TIMED> fin(a, x0, y0, dt, ax, ay, 2);
@@ -393,7 +392,8 @@ __device__ inline void stage_tile2d(const StageArgs<T, P>& a, int bid) {
 // TIMED: the grid's Hamiltonian may be the time- and phi-dependent family; the kernels of
 // every other family are compiled without its code.
 template <typename T, typename P, int STAGE, int TY, int S, bool TIMED>
-__global__ __launch_bounds__(threads2d(TY, S)) void k_stage2d(StageArgs<T, P> a) {
+__global__ __launch_bounds__(threads2d(TY, S), fp64_waves(sizeof(T), TY)) void k_stage2d(
+    StageArgs<T, P> a) {
     stage_tile2d<T, P, STAGE, TY, S, TIMED>(a, int(blockIdx.x));
 }
 

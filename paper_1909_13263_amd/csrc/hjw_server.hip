@@ -40,7 +40,7 @@ namespace hjw {
 // each XCD (dealt workgroups round-robin) works through one contiguous run of tiles and
 // their shared halos stay in its L2.
 template <typename T, typename P, int STAGE, int S>
-__global__ __launch_bounds__(threads2d(16, S)) void k_stage2d_batch(const StageArgs<T, P>* table,
+__global__ __launch_bounds__(threads2d(16, S), fp64_waves(sizeof(T), 16)) void k_stage2d_batch(const StageArgs<T, P>* table,
                                                                    const int* tile_start,
                                                                    const int* ngrids, int flip,
                                                                    int plan_ready) {

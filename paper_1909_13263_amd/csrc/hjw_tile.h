@@ -90,6 +90,8 @@ constexpr int kTX = 64;
 constexpr int kTX1 = 1024, kS1 = 4;
 // Threads of a 2-D workgroup: as many row threads as column threads.
 constexpr int threads2d(int ty, int seg) { return 2 * (kTX / seg) * ty; }
+// Waves per SIMD asked of the FP64 16-row stage kernels (3 tiles a CU; VGPRs <= 168).
+constexpr int fp64_waves(int elem, int ty) { return elem == 8 && ty == 16 ? 3 : 1; }
 
 // Step state kept on the device so that whole steps can be replayed from a graph.
 struct DevState {
@@ -164,6 +166,14 @@ __host__ __device__ inline double mul_rn(double a, double b) {
 #pragma clang fp contract(off)
     return a * b;
 }
+// Fused multiply-adds written out.  Together with mul_rn they leave the compiler no
+// choice of which product to fuse into which sum: a choice it makes from the use counts
+// and placement of the products, which differ between the instantiations of one march.
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ inline float fma_t(float a, float b, float c) { return std::fma(a, b, c); }
+__host__ __device__ inline double fma_t(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+}
 
 template <typename T>
 __host__ __device__ inline bool finite_t(T x) {
@@ -187,18 +197,18 @@ __host__ __device__ inline double mean2sq_series(double sg, double dl, double q4
     const double g = dl / q4;
     xx = dl * g;
     const double g2 = g * g;
-    const double s2 = sg * sg;
-    const double inner =
-        (2.0 / 3.0) + g2 * (0.4 * (s2 - 1.0) + g2 * ((2.0 / 7.0) * (s2 * (s2 - 6.0) + 2.0)));
-    const double X = 1.0 + g2 * inner;
+    const double s2 = mul_rn(sg, sg);
+    const double t3 = (2.0 / 7.0) * fma_t(s2, s2 - 6.0, 2.0);
+    const double inner = fma_t(g2, fma_t(g2, t3, mul_rn(0.4, s2 - 1.0)), 2.0 / 3.0);
+    const double X = fma_t(g2, inner, 1.0);
     return mul_rn(q4 * X, X);   // rounded alone: the weights add eps to it on every path
 }
 __host__ __device__ inline float mean2sq_series(float sg, float dl, float q4, float& xx) {
     const float g = dl * rcp_t(q4);
     xx = dl * g;
     const float g2 = g * g;
-    const float inner = (2.0f / 3.0f) + g2 * (0.4f * (sg * sg - 1.0f));
-    const float X = 1.0f + g2 * inner;
+    const float inner = fma_t(g2, 0.4f * fma_t(sg, sg, -1.0f), 2.0f / 3.0f);
+    const float X = fma_t(g2, inner, 1.0f);
     return mul_rn(q4 * X, X);
 }
 
@@ -208,19 +218,19 @@ __host__ __device__ inline float mean2sq_series(float sg, float dl, float q4, fl
 // gap use it, so that the difference of two values is divided by a gap of at least
 // tau sqrt(4 + sg^2): the rounding is amplified by a small factor only.
 __host__ __device__ inline double prim(double s) {
-    const double r = sqrt_t(1.0 + s * s);
-    return 0.5 * (s * r + copysign(log_t(fabs(s) + r), s));
+    const double r = sqrt_t(fma_t(s, s, 1.0));
+    return 0.5 * fma_t(s, r, copysign(log_t(fabs(s) + r), s));
 }
 // FP32: the same from the hardware square root and base-2 logarithm (about 1 ulp each).
 __device__ inline float prim(float s) {
     const float r = __builtin_amdgcn_sqrtf(fmaf(s, s, 1.0f));
     const float l = __builtin_amdgcn_logf(fabsf(s) + r) * 0.693147180559945309f;
-    return 0.5f * (s * r + copysignf(l, s));
+    return 0.5f * fma_t(s, r, copysignf(l, s));
 }
 __host__ inline float prim(float s) {
     const float r = std::sqrt(std::fma(s, s, 1.0f));
     const float l = std::log2(std::fabs(s) + r) * 0.693147180559945309f;
-    return 0.5f * (s * r + std::copysign(l, s));
+    return 0.5f * fma_t(s, r, std::copysign(l, s));
 }
 
 // Quotients: exact division in FP64; in FP32 a product with the hardware reciprocal.
@@ -231,6 +241,13 @@ __host__ __device__ inline T wdiv(T num, T den) {
 template <>
 __host__ __device__ inline float wdiv<float>(float num, float den) {
     return num * rcp_t(den);
+}
+// q + num / den: in FP32 one fused multiply-add with the reciprocal.
+__host__ __device__ inline double add_quot(double q, double num, double den) {
+    return q + num / den;
+}
+__host__ __device__ inline float add_quot(float q, float num, float den) {
+    return fma_t(num, rcp_t(den), q);
 }
 
 // Squares of the doubled means for the three pairs of one cell: (c0, b1), (c0, c1),
@@ -245,7 +262,7 @@ __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA2, T& MB
     const T sA = c0 + b1, dA = b1 - c0;
     const T sB = c0 + c1, dB = c1 - c0;
     const T sC = f0 + c1, dC = c1 - f0;
-    const T qA = sA * sA + T(4), qB = sB * sB + T(4), qC = sC * sC + T(4);
+    const T qA = fma_t(sA, sA, T(4)), qB = fma_t(sB, sB, T(4)), qC = fma_t(sC, sC, T(4));
     // half-gap dl/2 against tau sqrt(1 + m^2) = tau sqrt(q4)/2: wide when dl^2/q4 >= tau^2
     T xA, xB, xC;
     MA2 = mean2sq_series(sA, dA, qA, xA);
@@ -275,12 +292,12 @@ __host__ __device__ inline void cell_means(T c0, T b1, T c1, T f0, T& MA2, T& MB
 // as for WENO-L, the same three serve phi^-_i and, reversed, phi^+_{i-1}.
 template <typename T>
 __host__ __device__ inline void jp_indicators(T e1, T e2, T e3, T e4, T& IA, T& IB, T& IC) {
-    const T a0 = e1 - e2, a1 = e1 - T(3) * e2;
+    const T a0 = e1 - e2, a1 = fma_t(T(-3), e2, e1);
     const T b0 = e2 - e3, b1 = e2 + e3;
-    const T c0 = e3 - e4, c1 = T(3) * e3 - e4;
-    IA = T(13) * (a0 * a0) + T(3) * (a1 * a1);
-    IB = T(13) * (b0 * b0) + T(3) * (b1 * b1);
-    IC = T(13) * (c0 * c0) + T(3) * (c1 * c1);
+    const T c0 = e3 - e4, c1 = fma_t(T(3), e3, -e4);
+    IA = fma_t(T(13), a0 * a0, mul_rn(T(3), a1 * a1));
+    IB = fma_t(T(13), b0 * b0, mul_rn(T(3), b1 * b1));
+    IC = fma_t(T(13), c0 * c0, mul_rn(T(3), c1 * c1));
 }
 
 // Products of the weight denominators: with t_k = (eps/h^2 + M_k^2)^2 (up to a
@@ -314,7 +331,8 @@ __host__ __device__ inline void weight_products(float MA2, float MB2, float MC2,
 
 
 // March along one line.  line[k*stride] is phi_s at position p0-3+k,
-// k = 0..S+5; writes phi^-(p0+k) to um[k] and phi^+(p0+k) to up[k], k < S.
+// k = 0..S+5; hands phi^-(p0+k) to emit.minus(k, .) and phi^+(p0+k) to emit.plus(k, .),
+// k < S, as soon as the march has formed each (sweep() collects them in um[k], up[k]).
 // Differences are formed in the storage precision P and then cast to T.
 //
 // With v_j = Delta^+ phi_j and the cell [x_{i-1}, x_i] seeing (a,b,c,d,e) =
@@ -325,9 +343,9 @@ __host__ __device__ inline void weight_products(float MA2, float MB2, float MC2,
 //   q1 = c + (e2 + 2 e3)/6 for phi^- at x_i, and mirrored for phi^+ at x_{i-1}:
 //   qp1 = c - (e3 + 2 e2)/6, qp0 - qp1 = -D3b/3, qp2 - qp1 = -D3a/6.
 // So phi^- = q1 + (w0 (q0-q1) + w2 (q2-q1)) / (w0 + w1 + w2), and likewise phi^+.
-template <typename T, typename P, int S, int SCHEME>
-__host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T eps4, T* um,
-                                      T* up) {
+template <typename T, typename P, int S, int SCHEME, class Emit>
+__host__ __device__ inline void sweep_emit(const P* line, int stride, P ihP, T ih, T eps4,
+                                           Emit&& emit) {
     // The quotients are rounded on their own: fused into the differences that follow,
     // they would round differently at the ends of a segment than inside it.
     T v[S + 5];
@@ -358,23 +376,37 @@ __host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T 
         const T D3a = B1 - e3;                // a - 3b + 3c - d
         const T D3b = F0 - e2;                // b - 3c + 3d - e
         // numerators and denominators below are six times those of the weighted sums
-        const T xa = pBC * D3a, xb = pAB * D3b;
-        const T p36AC = T(36) * pAC;
+        const T xa = mul_rn(pBC, D3a), xb = mul_rn(pAB, D3b);
+        const T p36AC = mul_rn(T(36), pAC);
         if (it < S) {  // phi^- at node i: weights (1/10, 6/10, 3/10) on (A, B, C)
-            const T q1 = c + (e2 + T(2) * e3) * T(1.0 / 6.0);
-            const T num = (xa + xa) + T(3) * xb;                // 6 (pBC D3a/3 + pAB D3b/2)
-            um[it] = q1 + wdiv(num, (T(6) * pBC + p36AC) + T(18) * pAB);
+            const T q1 = fma_t(e2 + T(2) * e3, T(1.0 / 6.0), c);
+            const T num = fma_t(T(3), xb, xa + xa);             // 6 (pBC D3a/3 + pAB D3b/2)
+            const T den = fma_t(T(18), pAB, fma_t(T(6), pBC, p36AC));
+            emit.minus(it, add_quot(q1, num, den));
         }
         if (it > 0) {  // phi^+ at node i-1: the mirrored sub-stencils, (1/10, 6/10, 3/10) on (C, B, A)
-            const T qp1 = c - (e3 + T(2) * e2) * T(1.0 / 6.0);
-            const T num = (xb + xb) + T(3) * xa;                // 6 (pAB D3b/3 + pBC D3a/2)
-            up[it - 1] = qp1 - wdiv(num, (T(6) * pAB + p36AC) + T(18) * pBC);
+            const T qp1 = fma_t(-(e3 + T(2) * e2), T(1.0 / 6.0), c);
+            const T num = fma_t(T(3), xa, xb + xb);             // 6 (pAB D3b/3 + pBC D3a/2)
+            const T den = fma_t(T(18), pBC, fma_t(T(6), pAB, p36AC));
+            emit.plus(it - 1, add_quot(qp1, -num, den));
         }
         e1 = e2;
         e2 = e3;
         e3 = e4;
         c0 = c1;
     }
+}
+template <typename T>
+struct ToArrays {
+    T* um;
+    T* up;
+    __host__ __device__ void minus(int k, T v) const { um[k] = v; }
+    __host__ __device__ void plus(int k, T v) const { up[k] = v; }
+};
+template <typename T, typename P, int S, int SCHEME>
+__host__ __device__ inline void sweep(const P* line, int stride, P ihP, T ih, T eps4, T* um,
+                                      T* up) {
+    sweep_emit<T, P, S, SCHEME>(line, stride, ihP, ih, eps4, ToArrays<T>{um, up});
 }
 
 // ---------------------------------------------------------------- Hamiltonians
@@ -875,53 +907,56 @@ struct Tile {
         }
     }
 
-    // Phase X, t in [0, kHalf): (row, segment); phi_x^- / phi_x^+ into uL[0|1][row][x].
+    // Phase X, t in [0, kHalf): (row, segment); phi_x^- / phi_x^+ into uL[0|1][row][x],
+    // each stored as soon as the march forms it (no segment of results held in registers).
     __host__ __device__ static void sweep_x(int t, const StageArgs<T, P>& a, const P* phiL,
                                             T* uL) {
         const int row = t % TY;
         const int seg = t / TY;
-        T um[SX], up[SX];
-        // the scheme is uniform over the launch: one branch around the whole march
+        struct ToLds {
+            T* base;
+            __host__ __device__ void minus(int k, T v) const { base[k] = v; }
+            __host__ __device__ void plus(int k, T v) const { base[TY * UW + k] = v; }
+        };
+        const ToLds out{uL + row * UW + seg * SX};
         if (a.scheme == kSchemeJP)
-            sweep<T, P, SX, kSchemeJP>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT, a.epsx,
-                                       um, up);
+            sweep_emit<T, P, SX, kSchemeJP>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT,
+                                            a.epsx, out);
         else
-            sweep<T, P, SX, kSchemeL>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT, a.epsx,
-                                      um, up);
-#pragma unroll
-        for (int k = 0; k < SX; ++k) {
-            uL[row * UW + seg * SX + k] = um[k];
-            uL[TY * UW + row * UW + seg * SX + k] = up[k];
-        }
+            sweep_emit<T, P, SX, kSchemeL>(phiL + (row + 3) * PW + seg * SX, 1, a.ihx, a.ihxT,
+                                           a.epsx, out);
     }
 
-    // Phase Y, t in [0, kHalf): (column, segment); phi_y^- / phi_y^+ into registers.
-    __host__ __device__ static void sweep_y(int t, const StageArgs<T, P>& a, const P* phiL, T* vm,
-                                            T* vp) {
-        const int col = t % TX;
-        const int seg = t / TX;
-        if (a.scheme == kSchemeJP)
-            sweep<T, P, SY, kSchemeJP>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy,
-                                       vm, vp);
-        else
-            sweep<T, P, SY, kSchemeL>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT, a.epsy,
-                                      vm, vp);
-    }
-
-    // The finish is shared by all threads: a column thread keeps the first SY/2 of its
-    // nodes and, before the barrier, stashes phi_y^-+ of the other SY/2 in vL, where
-    // the row thread of the same index picks them up.
+    // The finish is shared by all threads: a column thread keeps phi_y^-+ of the first
+    // SY/2 of its nodes in registers and stashes those of the other SY/2 in vL, where the
+    // row thread of the same index picks them up after the barrier.
     static constexpr int kKeep = SY / 2;
     static constexpr int kVElems = 2 * TY * TX / 2;
-    __host__ __device__ static void stash(int t, const T* vm, const T* vp, T* vL) {
+
+    // Phase Y, t in [0, kHalf): (column, segment); phi_y^- / phi_y^+ of the kept nodes into
+    // vm / vp, of the others into the stash, each as soon as the march forms it.
+    __host__ __device__ static void sweep_y(int t, const StageArgs<T, P>& a, const P* phiL, T* vm,
+                                            T* vp, T* vL) {
         const int col = t % TX;
         const int seg = t / TX;
-        T* v0 = vL + seg * kKeep * TX + col;
-#pragma unroll
-        for (int k = kKeep; k < SY; ++k) {
-            v0[(k - kKeep) * TX] = vm[k];
-            v0[kVElems / 2 + (k - kKeep) * TX] = vp[k];
-        }
+        struct KeepOrStash {
+            T* vm;
+            T* vp;
+            T* v0;
+            __host__ __device__ void minus(int k, T v) const {
+                if (k < kKeep) vm[k] = v; else v0[(k - kKeep) * TX] = v;
+            }
+            __host__ __device__ void plus(int k, T v) const {
+                if (k < kKeep) vp[k] = v; else v0[kVElems / 2 + (k - kKeep) * TX] = v;
+            }
+        };
+        const KeepOrStash out{vm, vp, vL + seg * kKeep * TX + col};
+        if (a.scheme == kSchemeJP)
+            sweep_emit<T, P, SY, kSchemeJP>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT,
+                                            a.epsy, out);
+        else
+            sweep_emit<T, P, SY, kSchemeL>(phiL + seg * SY * PW + col + 3, PW, a.ihy, a.ihyT,
+                                           a.epsy, out);
     }
 
     // After the barrier: fin(col, row, um, up, vm, vp, phi_s, phi^n) for SY/2 nodes of
