@@ -67,39 +67,47 @@ def kernel_bytes_per_cell(phi_b, flux_b):
 # (SQ_INSTS_VALU_* x 64 / nodes).  Valid only while the kernel sources hash to the recorded
 # SHA-256; after any change the counter-derived fields are null until re-measured.
 MEASURED = {
-    "source_sha256": "f8c4da55030f36ec690cc75582491ea29dc9c007f00fa5dc448bc3dbac1daa44",
+    "source_sha256": "cfc9faa4c751c743d53d3b32d2b35723fe6daf266cad6743c697fcb608e3db64",
     "runs": {
         "fp32_stencil/1024": {
-            "pre": {"fetch_kib": 4559.7, "write_kib": 12416.0, "traffic_bytes": 22052324,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 22.71, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.81}},
-            "mid": {"fetch_kib": 11018.0, "write_kib": 8192.1, "traffic_bytes": 30953676,
-                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 17.75, "cvt": 10.25, "i64": 3.86, "trans_f32": 13.25, "trans_f64": 0.06, "other": 33.66}},
-            "last": {"fetch_kib": 8639.0, "write_kib": 8194.2, "traffic_bytes": 26083584,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 15.34, "cvt": 5.25, "i64": 2.39, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.55}},
+            "pre": {"fetch_kib": 4562.1, "write_kib": 12416.0, "traffic_bytes": 22057064,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 21.71, "cvt": 4.75, "i64": 2.36, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.81}},
+            "mid": {"fetch_kib": 11013.0, "write_kib": 8192.1, "traffic_bytes": 30943436,
+                    "valu_per_node": {"f32": 182.0, "f64": 17.88, "i32": 16.88, "cvt": 10.25, "i64": 3.86, "trans_f32": 13.25, "trans_f64": 0.06, "other": 33.53}},
+            "last": {"fetch_kib": 8636.0, "write_kib": 8194.2, "traffic_bytes": 26077440,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 14.34, "cvt": 5.25, "i64": 2.39, "trans_f32": 13.25, "trans_f64": 0.0, "other": 30.55}},
         },
         "fp32_stencil/2048": {
-            "pre": {"fetch_kib": 17063.1, "write_kib": 49664.0, "traffic_bytes": 85801064,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 22.39, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.38}},
-            "mid": {"fetch_kib": 42210.5, "write_kib": 32768.0, "traffic_bytes": 120001479,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 15.13, "cvt": 9.75, "i64": 2.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.15}},
-            "last": {"fetch_kib": 33423.5, "write_kib": 32770.2, "traffic_bytes": 102007993,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 14.92, "cvt": 5.25, "i64": 1.83, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.91}},
+            "pre": {"fetch_kib": 17072.0, "write_kib": 49664.0, "traffic_bytes": 85819359,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 21.39, "cvt": 4.75, "i64": 2.06, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.38}},
+            "mid": {"fetch_kib": 42201.0, "write_kib": 32768.0, "traffic_bytes": 119982123,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 14.25, "cvt": 9.75, "i64": 2.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 28.02}},
+            "last": {"fetch_kib": 33424.3, "write_kib": 32770.2, "traffic_bytes": 102009614,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 13.92, "cvt": 5.25, "i64": 1.83, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.91}},
         },
         "fp32_stencil/4096": {
-            "pre": {"fetch_kib": 66683.7, "write_kib": 198656.0, "traffic_bytes": 339991893,
-                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 22.23, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.16}},
-            "mid": {"fetch_kib": 166147.0, "write_kib": 131072.0, "traffic_bytes": 474486846,
-                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 15.13, "cvt": 9.75, "i64": 2.7, "trans_f32": 13.25, "trans_f64": 0.0, "other": 27.95}},
-            "last": {"fetch_kib": 132150.5, "write_kib": 131074.2, "traffic_bytes": 404864251,
-                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 14.71, "cvt": 5.25, "i64": 1.54, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.58}},
+            "pre": {"fetch_kib": 66693.6, "write_kib": 198656.0, "traffic_bytes": 340012260,
+                    "valu_per_node": {"f32": 178.0, "f64": 6.5, "i32": 21.23, "cvt": 4.75, "i64": 1.91, "trans_f32": 13.25, "trans_f64": 0.0, "other": 38.16}},
+            "mid": {"fetch_kib": 166139.6, "write_kib": 131072.0, "traffic_bytes": 474471718,
+                    "valu_per_node": {"f32": 182.0, "f64": 16.0, "i32": 14.25, "cvt": 9.75, "i64": 2.7, "trans_f32": 13.25, "trans_f64": 0.0, "other": 27.82}},
+            "last": {"fetch_kib": 132151.2, "write_kib": 131074.2, "traffic_bytes": 404865673,
+                    "valu_per_node": {"f32": 182.0, "f64": 9.5, "i32": 13.71, "cvt": 5.25, "i64": 1.54, "trans_f32": 13.25, "trans_f64": 0.0, "other": 29.58}},
         },
         "fp64/1024": {
-            "pre": {"fetch_kib": 4732.5, "write_kib": 24704.0, "traffic_bytes": 34989118,
-                    "valu_per_node": {"f32": 0.25, "f64": 279.75, "i32": 15.21, "cvt": 0.5, "i64": 2.36, "trans_f32": 0.25, "trans_f64": 10.75, "other": 113.69}},
-            "mid": {"fetch_kib": 17681.6, "write_kib": 8192.1, "traffic_bytes": 44600690,
-                    "valu_per_node": {"f32": 0.25, "f64": 295.12, "i32": 15.97, "cvt": 0.5, "i64": 3.55, "trans_f32": 0.25, "trans_f64": 10.81, "other": 76.15}},
-            "last": {"fetch_kib": 8829.5, "write_kib": 8194.2, "traffic_bytes": 26473737,
-                    "valu_per_node": {"f32": 0.25, "f64": 286.75, "i32": 14.84, "cvt": 0.5, "i64": 2.39, "trans_f32": 0.25, "trans_f64": 10.75, "other": 66.67}},
+            "pre": {"fetch_kib": 4881.3, "write_kib": 25720.9, "traffic_bytes": 36335066,
+                    "valu_per_node": {"f32": 0.25, "f64": 280.0, "i32": 14.33, "cvt": 0.5, "i64": 2.48, "trans_f32": 0.25, "trans_f64": 10.75, "other": 108.94}},
+            "mid": {"fetch_kib": 17782.7, "write_kib": 10188.0, "traffic_bytes": 46851518,
+                    "valu_per_node": {"f32": 0.25, "f64": 295.5, "i32": 15.22, "cvt": 0.5, "i64": 3.67, "trans_f32": 0.25, "trans_f64": 10.81, "other": 71.4}},
+            "last": {"fetch_kib": 8863.4, "write_kib": 9866.1, "traffic_bytes": 28255028,
+                    "valu_per_node": {"f32": 0.25, "f64": 287.12, "i32": 13.96, "cvt": 0.5, "i64": 2.52, "trans_f32": 0.25, "trans_f64": 10.75, "other": 61.92}},
+        },
+        "fp64/2048": {
+            "pre": {"fetch_kib": 17992.9, "write_kib": 102877.7, "traffic_bytes": 142196172,
+                    "valu_per_node": {"f32": 0.25, "f64": 280.0, "i32": 14.02, "cvt": 0.5, "i64": 2.18, "trans_f32": 0.25, "trans_f64": 10.75, "other": 108.51}},
+            "mid": {"fetch_kib": 68805.6, "write_kib": 40944.4, "traffic_bytes": 182840913,
+                    "valu_per_node": {"f32": 0.25, "f64": 293.62, "i32": 13.99, "cvt": 0.5, "i64": 2.38, "trans_f32": 0.25, "trans_f64": 10.75, "other": 58.97}},
+            "last": {"fetch_kib": 34431.2, "write_kib": 37658.6, "traffic_bytes": 109077438,
+                    "valu_per_node": {"f32": 0.25, "f64": 287.12, "i32": 13.55, "cvt": 0.5, "i64": 1.95, "trans_f32": 0.25, "trans_f64": 10.75, "other": 61.28}},
         },
     },
 }
