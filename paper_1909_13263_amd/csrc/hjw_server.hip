@@ -119,6 +119,23 @@ constexpr int kInFlight = 2;      // chunks queued on the stream at most
 // Bytes of phi0 (or of results) moved through one pinned staging buffer per processing
 // step; more waits for the next step (one solve larger than this always moves alone).
 constexpr size_t kStageCap = size_t(256) << 20;
+// Pinned host memory that queued phi0 arrays are copied into at submission, so that
+// admission copies them to the pool directly: a quarter of the pool, at most 1 GiB.
+constexpr size_t kInboxMax = size_t(1) << 30;
+
+// Copies n values and reports whether all are finite (exponent field not all ones): one
+// pass over the caller's array instead of a test and then a copy.
+bool copy_finite(double* dst, const double* src, int64_t n) {
+    constexpr uint64_t kExp = 0x7ff0000000000000ull;
+    uint64_t bad = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        uint64_t u;
+        std::memcpy(&u, src + k, sizeof u);
+        bad |= uint64_t((u & kExp) == kExp);
+        std::memcpy(dst + k, &u, sizeof u);
+    }
+    return bad == 0;
+}
 
 double seconds_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -177,6 +194,8 @@ struct Req {
     int64_t first_chunk = 0;   // the first chunk whose table holds this solve
     int res_buf = -1;          // pinned staging buffer holding its result (state 3)
     size_t res_off = 0;
+    size_t in_off = SIZE_MAX;  // its phi0 in the pinned inbox (else in phi0)
+    size_t in_bytes = 0;
 };
 
 // A pinned host buffer for copies between the pool and host memory that must not wait:
@@ -187,6 +206,7 @@ struct Staging {
     hipEvent_t ev = nullptr;
     bool pending = false;
     std::vector<int64_t> ids;   // results held (download buffers)
+    std::vector<std::pair<size_t, size_t>> inbox;   // inbox blocks read by its copies
 };
 
 struct GraphEntry {
@@ -278,6 +298,8 @@ struct hjw_server {
 
     size_t heap_off = 0, heap_bytes = 0, in_use = 0, peak = 0;
     PoolMap heap;
+    char* inbox = nullptr;   // pinned; blocks return once the copies reading them are done
+    PoolMap inbox_map;
     std::vector<int> free_slots;
     std::deque<int64_t> queue;
     std::vector<int64_t> active;  // table order
@@ -495,21 +517,29 @@ hjw_status finish_downloads(hjw_server* s, bool wait, int only = -1) {
     return HJW_OK;
 }
 
-// Admit waiting requests first-in first-out while a slot, pool space and room in this
-// step's upload staging (kStageCap, or one larger request alone) are free; phi0 is
-// copied in behind the queued chunks.
+// Inbox blocks read by the copies of an upload buffer whose event has completed.
+void reclaim_inbox(hjw_server* s, Staging& up) {
+    for (const auto& blk : up.inbox) s->inbox_map.release(blk.first, blk.second);
+    up.inbox.clear();
+}
+
+// Admit waiting requests first-in first-out while a slot and pool space are free, and
+// for phi0 not held in the inbox, room in this step's upload staging (kStageCap, or one
+// larger request alone); phi0 is copied in behind the queued chunks.
 hjw_status admit(hjw_server* s, Staging& up) {
     if (up.pending) {
         HIP_TRY(hipEventSynchronize(up.ev));
         up.pending = false;
     }
+    reclaim_inbox(s, up);
     std::vector<int64_t> take;
     size_t total = 0;
     for (int64_t id : s->queue) {
         Req& q = s->reqs.at(id);
-        const size_t nb = align256(size_t(q.cells) * sizeof(double));
+        const bool staged = q.in_off == SIZE_MAX;
+        const size_t nb = staged ? align256(size_t(q.cells) * sizeof(double)) : 0;
         if (take.size() >= s->free_slots.size()) break;
-        if (!take.empty() && total + nb > kStageCap) break;   // the next step takes it
+        if (staged && total > 0 && total + nb > kStageCap) break;   // the next step takes it
         const size_t off = s->heap.alloc(q.bytes);
         if (off == SIZE_MAX) break;  // first in, first out: wait for space
         q.off = off;
@@ -526,7 +556,7 @@ hjw_status admit(hjw_server* s, Staging& up) {
     for (int64_t id : take) {
         Req& q = s->reqs.at(id);
         const size_t n = size_t(q.cells);
-        char* src = up.p + q.res_off;
+        char* src = q.in_off == SIZE_MAX ? up.p + q.res_off : s->inbox + q.in_off;
         q.res_off = 0;
         q.slot = s->free_slots.back();
         s->free_slots.pop_back();
@@ -536,8 +566,13 @@ hjw_status admit(hjw_server* s, Staging& up) {
         q.first_chunk = s->next_chunk;
         s->in_use += q.bytes;
         s->peak = std::max(s->peak, s->in_use);
-        std::memcpy(src, q.phi0.data(), n * sizeof(double));
-        std::vector<double>().swap(q.phi0);
+        if (q.in_off == SIZE_MAX) {
+            std::memcpy(src, q.phi0.data(), n * sizeof(double));
+            std::vector<double>().swap(q.phi0);
+        } else {
+            up.inbox.emplace_back(q.in_off, q.in_bytes);   // returned after up.ev
+            q.in_off = SIZE_MAX;
+        }
         char* w = s->base + s->heap_off + q.off;
         if (s->prec == HJW_FP32) {
             double* stage = reinterpret_cast<double*>(w + 2 * align256(n * 4));
@@ -749,6 +784,17 @@ hjw_status hjw_server_create(int prec, void* pool, size_t pool_bytes, int max_ac
     s->heap_off = o;
     s->heap_bytes = pool_bytes - o;
     s->heap.reset(s->heap_bytes / 256 * 256);
+    // the inbox is an optimisation: without it phi0 waits in ordinary host memory
+    const size_t inbox = std::min(kInboxMax, s->heap_bytes / 4 / 256 * 256);
+    if (inbox >= (size_t(1) << 20)) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&s->inbox), inbox, hipHostMallocDefault) ==
+            hipSuccess) {
+            s->inbox_map.reset(inbox);
+        } else {
+            s->inbox = nullptr;
+            (void)hipGetLastError();   // leave no error behind for the next check
+        }
+    }
     for (int k = max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
     hjw_status st = HJW_OK;
     s->stream = static_cast<hipStream_t>(stream);
@@ -803,12 +849,36 @@ hjw_status hjw_server_submit(hjw_server* s, const hjw_request* req, const double
         return fail(HJW_ENOMEM, "request needs %zu pool bytes, the pool has %zu", bytes,
                     s->heap_bytes);
     const int64_t n = req->n[0] * req->n[1];
-    for (int64_t k = 0; k < n; ++k)
-        if (!std::isfinite(phi0[k])) return fail(HJW_ENONFINITE, "phi0 holds non-finite values");
     Req q;
+    // phi0 goes to the pinned inbox when a block is free (after returning the blocks of
+    // uploads that have completed), else to host memory of its own
+    const size_t in_bytes = align256(size_t(n) * sizeof(double));
+    if (s->inbox) {
+        q.in_off = s->inbox_map.alloc(in_bytes);
+        for (int b = 0; b < 2 && q.in_off == SIZE_MAX; ++b) {
+            Staging& up = s->up[b];
+            if (!up.pending) continue;
+            const hipError_t e = hipEventQuery(up.ev);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return fail(HJW_EHIP, "hipEventQuery: %s", hipGetErrorString(e));
+            up.pending = false;
+            reclaim_inbox(s, up);
+            q.in_off = s->inbox_map.alloc(in_bytes);
+        }
+    }
+    if (q.in_off != SIZE_MAX) {
+        q.in_bytes = in_bytes;
+        if (!copy_finite(reinterpret_cast<double*>(s->inbox + q.in_off), phi0, n)) {
+            s->inbox_map.release(q.in_off, in_bytes);
+            return fail(HJW_ENONFINITE, "phi0 holds non-finite values");
+        }
+    } else {
+        q.phi0.resize(size_t(n));
+        if (!copy_finite(q.phi0.data(), phi0, n))
+            return fail(HJW_ENONFINITE, "phi0 holds non-finite values");
+    }
     q.id = s->next_id++;
     q.r = *req;
-    q.phi0.assign(phi0, phi0 + n);
     q.t_submit = seconds_since(s->t0);
     q.bytes = bytes;
     q.cells = n;
@@ -901,6 +971,7 @@ void hjw_server_destroy(hjw_server* s) {
         unpin(s->h_rec[b]);
         drop(s->rec_ev[b]);
     }
+    unpin(s->inbox);
     if (s->capture) (void)hipStreamDestroy(s->capture);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;

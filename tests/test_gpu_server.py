@@ -234,8 +234,9 @@ def test_mixed_schemes_in_one_batch():
 
 def test_bursts_larger_than_one_staging_step():
     """Forty 1200^2 solves (11.5 MB of phi0 and of result each, 460 MB in all) submitted at
-    once: admission and retirement move at most 256 MiB through pinned staging per step, so
-    the burst is admitted over two steps, and the two groups (long horizons first, short
+    once: the pinned inbox (a quarter of the 1.4 GB pool) takes the phi0 of the first ~30,
+    the rest wait in host memory and are admitted through pinned staging; retirement moves
+    at most 256 MiB through staging per step, so the two groups (long horizons first, short
     ones second) finish in the same chunk and retire over two steps.  Every result is the
     single-grid result of its own phi0, bit for bit."""
     n = 1200
