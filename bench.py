@@ -182,6 +182,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the measured saturation rate")
+    ap.add_argument("--serve-fixed-rate", type=float, default=190.0,
+                    help="also replay the stream at this fixed arrival rate (requests/s; "
+                         "0 skips): a load that does not move with the saturation rate")
     ap.add_argument("--serve-pool-gib", type=float, default=4.0)
     ap.add_argument("--serve-max-active", type=int, default=256)
     ap.add_argument("--serve-sustain-sample", type=int, default=768,
@@ -502,6 +505,15 @@ def served_stream(args, hjw):
     wall = time.perf_counter() - t1
     after = srv.stats()
     summary = S.summarize(recs, wall)
+    fixed = None
+    if args.serve_fixed_rate > 0:
+        t2 = time.perf_counter()
+        recs2 = S.run_stream(srv, reqs, phi0s, time_scale=1.0 / args.serve_fixed_rate)
+        s2 = S.summarize(recs2, time.perf_counter() - t2)
+        fixed = {"arrival_rate_rps": args.serve_fixed_rate, "failed": s2["failed"],
+                 "p50_ms": s2["p50_ms"], "p90_ms": s2["p90_ms"], "p99_ms": s2["p99_ms"],
+                 "max_ms": s2["max_ms"],
+                 "cell_updates_per_s": s2["cell_updates"] / s2["wall_s"]}
     srv.close()
     return {
         "requests": summary["requests"], "failed": summary["failed"],
@@ -521,6 +533,7 @@ def served_stream(args, hjw):
         "pool_gib": args.serve_pool_gib, "pool_peak_gib": after["pool_peak"] / (1 << 30),
         "max_active": args.serve_max_active, "phi0_prep_s": prep,
         "latency_from": "scheduled arrival to result in host memory",
+        "fixed_rate": fixed,
     }
 
 

@@ -274,11 +274,14 @@ typedef struct {
 hjw_status hjw_server_footprint(int prec, const hjw_request *req, size_t *bytes);
 
 /* Create a server over a caller-owned device pool (256-byte aligned) for up to
- * max_active concurrent solves (1..1024); hip_stream as for hjw_bind. */
+ * max_active concurrent solves (1..1024); hip_stream as for hjw_bind.  The server also
+ * pins host memory of its own: pinned staging for uploads and results, and an inbox for
+ * queued phi0 of a quarter of the pool (at most 1 GiB; none if pinning fails). */
 hjw_status hjw_server_create(int prec, void *dev_pool, size_t pool_bytes, int max_active,
                              void *hip_stream, hjw_server **out);
 
-/* Queue a request with phi0 (FP64 host array of n[0]*n[1] values, copied).
+/* Queue a request with phi0 (FP64 host array of n[0]*n[1] values, copied before the
+ * call returns: into the pinned inbox when it has room, else into host memory).
  * HJW_ENOMEM if the request could never fit the pool.  *id receives its id. */
 hjw_status hjw_server_submit(hjw_server *s, const hjw_request *req, const double *phi0,
                              int64_t *id);

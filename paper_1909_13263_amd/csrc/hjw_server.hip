@@ -789,6 +789,9 @@ hjw_status hjw_server_create(int prec, void* pool, size_t pool_bytes, int max_ac
     if (inbox >= (size_t(1) << 20)) {
         if (hipHostMalloc(reinterpret_cast<void**>(&s->inbox), inbox, hipHostMallocDefault) ==
             hipSuccess) {
+            // touch every page now: the first writes to fresh pinned pages cost a page
+            // fault each, which would otherwise fall on the first burst of submissions
+            std::memset(s->inbox, 0, inbox);
             s->inbox_map.reset(inbox);
         } else {
             s->inbox = nullptr;
