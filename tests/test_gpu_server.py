@@ -232,6 +232,38 @@ def test_mixed_schemes_in_one_batch():
         assert np.array_equal(results[sid].phi, ref), (pr.name, pr.shape, sc)
 
 
+def test_phi0_is_checked_on_both_submission_paths():
+    """phi0 is copied at submission either into the pinned inbox (a quarter of the pool) or,
+    when it does not fit there, into host memory; both copies test every value.  A single
+    infinity at the last node or in the middle is refused on either path, and requests that
+    pass solve to their single-grid results."""
+    srv = hjw.Server(MIXED, pool_bytes=24 << 20, max_active=2)   # inbox 6 MiB
+    small = W.burgers2d(64, 0.01)       # 32 KB of phi0: the inbox
+    big = W.burgers2d(900, 0.002)       # 6.5 MB of phi0: host memory
+    for pr in (small, big):
+        for where in (-1, pr.shape[0] * pr.shape[1] // 2):
+            phi = pr.phi0().copy()
+            phi.flat[where] = np.inf if where < 0 else -np.inf
+            with pytest.raises(hjw.HJWError) as e:
+                srv.submit(pr, phi)
+            assert e.value.code == hjw.ENONFINITE
+    srv.submit(big)
+    srv.submit(small)
+    done = srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert len(done) == 2 and st["done"] == 2 and st["pool_in_use"] == 0
+    for res in done:
+        pr = big if res.phi.shape == big.shape else small
+        g = hjw.grid_for(pr, MIXED)
+        g.set_phi(pr.phi0())
+        info = g.step_to(pr.t_final, pr.cfl)
+        ref = g.get_phi()
+        g.close()
+        assert res.status == hjw.OK and res.info.steps == info.steps
+        assert np.array_equal(res.phi, ref)
+
+
 def test_bursts_larger_than_one_staging_step():
     """Forty 1200^2 solves (11.5 MB of phi0 and of result each, 460 MB in all) submitted at
     once: the pinned inbox (a quarter of the 1.4 GB pool) takes the phi0 of the first ~30,
